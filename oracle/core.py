@@ -1,0 +1,207 @@
+"""ctypes wrapper around the C oracle (``mp_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: see the package docstring.  Every routine is FP64.
+"""
+import ctypes as C
+from dataclasses import dataclass
+from typing import Sequence
+
+import numpy as np
+
+from . import build as _build
+
+WIN_BLACKMAN = 0
+WIN_HANN = 1
+THR_REL = 1
+CONJ_GATE_GAMMA = 2
+
+STOP_K, STOP_SNR, STOP_ENEG, STOP_ZERO = 1, 2, 3, 4
+
+
+class _Dict(C.Structure):
+    _fields_ = [("window", C.c_int32), ("gl", C.c_int32), ("a", C.c_int32),
+                ("M", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("stop_reason", C.c_int32),
+                ("pad_", C.c_int32), ("L_padded", C.c_int64), ("E0", C.c_double),
+                ("E_final", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(_build.build())
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        _lib.orc_window.argtypes = [C.c_int32, C.c_int32, dp]
+        _lib.orc_check_dicts.argtypes = [C.POINTER(_Dict), C.c_int32]
+        _lib.orc_padded_length.argtypes = [C.POINTER(_Dict), C.c_int32, C.c_int64]
+        _lib.orc_padded_length.restype = C.c_int64
+        _lib.orc_fft.argtypes = [C.c_int32, dp, dp, C.c_int32]
+        _lib.orc_dgt.argtypes = [C.POINTER(_Dict), dp, C.c_int64, dp, dp]
+        _lib.orc_dgt_direct.argtypes = [C.POINTER(_Dict), dp, C.c_int64, dp, dp]
+        _lib.orc_kernel_direct.argtypes = [C.POINTER(_Dict), C.POINTER(_Dict),
+                                           C.c_int64, C.c_int64,
+                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        _lib.orc_kernel_table.argtypes = [C.POINTER(_Dict), C.POINTER(_Dict), C.c_double,
+                                          C.c_uint32, C.POINTER(C.c_int32), C.c_void_p,
+                                          C.c_void_p, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32)]
+        _lib.orc_mp.argtypes = [C.POINTER(_Dict), C.c_int32, dp, C.c_int64, C.c_double,
+                                C.c_uint32, C.c_int64, C.c_double, C.c_int64, ip, ip, ip,
+                                dp, dp, dp, dp, C.c_void_p, C.c_void_p, C.POINTER(_Stats)]
+        _lib.orc_resynth.argtypes = [C.POINTER(_Dict), C.c_int32, C.c_int64, C.c_int64,
+                                     ip, ip, ip, dp, dp, dp]
+    return _lib
+
+
+def _dicts(dicts: Sequence[Sequence[int]]):
+    arr = (_Dict * len(dicts))()
+    for i, d in enumerate(dicts):
+        arr[i] = _Dict(*[int(v) for v in d])
+    return arr
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError("oracle error %d" % rc)
+
+
+def window(win: int, gl: int) -> np.ndarray:
+    g = np.zeros(gl)
+    _check(lib().orc_window(win, gl, g))
+    return g
+
+
+def check_dicts(dicts) -> int:
+    return lib().orc_check_dicts(_dicts(dicts), len(dicts))
+
+
+def padded_length(dicts, L: int) -> int:
+    return lib().orc_padded_length(_dicts(dicts), len(dicts), L)
+
+
+def fft(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    re = np.ascontiguousarray(x.real, dtype=np.float64).copy()
+    im = np.ascontiguousarray(np.imag(x), dtype=np.float64).copy()
+    _check(lib().orc_fft(len(re), re, im, sign))
+    return re + 1j * im
+
+
+def dgt(d, x: np.ndarray, direct: bool = False) -> np.ndarray:
+    """Reduced DGT plane (N x M/2+1, complex128) of a real signal."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    L = len(x)
+    N, MR = L // d[2], d[3] // 2 + 1
+    re = np.zeros(N * MR)
+    im = np.zeros(N * MR)
+    f = lib().orc_dgt_direct if direct else lib().orc_dgt
+    _check(f(_dicts([d]), x, L, re, im))
+    return (re + 1j * im).reshape(N, MR)
+
+
+def kernel_direct(dw, dv, mu: int, Delta: int) -> complex:
+    re, im = C.c_double(), C.c_double()
+    _check(lib().orc_kernel_direct(_dicts([dw]), _dicts([dv]), mu, Delta,
+                                   C.byref(re), C.byref(im)))
+    return complex(re.value, im.value)
+
+
+@dataclass
+class KernelTable:
+    D: int
+    Mmax: int
+    amin: int
+    h: np.ndarray  # (2D+1, Mmax) complex128, column index delta + D
+    box_mu: int
+    box_delta: int
+
+
+def kernel_table(dw, dv, eps: float, flags: int = 0) -> KernelTable:
+    D = C.c_int32()
+    _check(lib().orc_kernel_table(_dicts([dw]), _dicts([dv]), eps, flags, C.byref(D),
+                                  None, None, None, None))
+    Mmax = max(dw[3], dv[3])
+    n = (2 * D.value + 1) * Mmax
+    re = np.zeros(n)
+    im = np.zeros(n)
+    bm, bd = C.c_int32(), C.c_int32()
+    _check(lib().orc_kernel_table(_dicts([dw]), _dicts([dv]), eps, flags, C.byref(D),
+                                  re.ctypes.data, im.ctypes.data, C.byref(bm),
+                                  C.byref(bd)))
+    return KernelTable(D.value, Mmax, min(dw[2], dv[2]),
+                       (re + 1j * im).reshape(2 * D.value + 1, Mmax), bm.value, bd.value)
+
+
+@dataclass
+class MPResult:
+    w: np.ndarray
+    m: np.ndarray
+    n: np.ndarray
+    c: np.ndarray
+    E: np.ndarray      # error estimate after each selection
+    gap: np.ndarray    # relative top-2 gap of |rho|^2 at each selection
+    E0: float
+    L_padded: int
+    stop_reason: int
+    planes: list       # final residual planes per system (or None)
+
+    @property
+    def n_atoms(self):
+        return len(self.w)
+
+
+def mp(dicts, x: np.ndarray, eps: float, K: int = 0, target_db: float = 0.0,
+       flags: int = 0, cap: int = None, return_planes: bool = False) -> MPResult:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    L = len(x)
+    Lp = padded_length(dicts, L)
+    if Lp < 0:
+        raise RuntimeError("oracle error %d" % Lp)
+    kmax = K if K > 0 else Lp // 5
+    if cap is None:
+        cap = kmax
+    cap = max(int(cap), 1)
+    aw = np.zeros(cap, np.int32)
+    am = np.zeros(cap, np.int32)
+    an = np.zeros(cap, np.int32)
+    cre = np.zeros(cap)
+    cim = np.zeros(cap)
+    Ea = np.zeros(cap)
+    gp = np.zeros(cap)
+    sizes = [(Lp // d[2]) * (d[3] // 2 + 1) for d in dicts]
+    fr = fi = None
+    if return_planes:
+        fr = np.zeros(sum(sizes))
+        fi = np.zeros(sum(sizes))
+    st = _Stats()
+    _check(lib().orc_mp(_dicts(dicts), len(dicts), x, L, eps, flags, K, target_db, cap,
+                        aw, am, an, cre, cim, Ea, gp,
+                        fr.ctypes.data if fr is not None else None,
+                        fi.ctypes.data if fi is not None else None, C.byref(st)))
+    k = st.n_atoms
+    planes = None
+    if return_planes:
+        planes, o = [], 0
+        for d, s in zip(dicts, sizes):
+            planes.append((fr[o:o + s] + 1j * fi[o:o + s]).reshape(Lp // d[2], d[3] // 2 + 1))
+            o += s
+    return MPResult(aw[:k].copy(), am[:k].copy(), an[:k].copy(), cre[:k] + 1j * cim[:k],
+                    Ea[:k].copy(), gp[:k].copy(), st.E0, st.L_padded, st.stop_reason,
+                    planes)
+
+
+def resynth(dicts, Lp: int, w, m, n, c) -> np.ndarray:
+    w = np.ascontiguousarray(w, np.int32)
+    m = np.ascontiguousarray(m, np.int32)
+    n = np.ascontiguousarray(n, np.int32)
+    c = np.asarray(c, np.complex128)
+    y = np.zeros(Lp)
+    _check(lib().orc_resynth(_dicts(dicts), len(dicts), Lp, len(w), w, m, n,
+                             np.ascontiguousarray(c.real), np.ascontiguousarray(c.imag), y))
+    return y

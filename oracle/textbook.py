@@ -1,0 +1,80 @@
+"""Textbook matching pursuit in the signal domain (numpy, tiny signals only).
+
+TEST INFRASTRUCTURE ONLY.  Every iteration recomputes all inner products of the
+residual with every atom of the reduced multi-Gabor dictionary from explicitly
+built atoms, selects the largest |<r, d_p>| (Sec. 2.2, non-pedantic selection
+of Sec. 5), and subtracts the least-squares projection onto the real atom pair
+{d, conj d} (Sec. 5, the pair treatment of real signals).  No Gram matrix, no
+kernel and no truncation is involved, so with a zero kernel threshold the
+coefficient-domain oracle must reproduce this sequence exactly.
+"""
+import numpy as np
+
+
+def _window(win: int, gl: int) -> np.ndarray:
+    # independent restatement of the centred periodic windows, unit 2-norm
+    t = np.arange(gl) - gl // 2
+    if win == 0:
+        g = 0.42 + 0.5 * np.cos(2 * np.pi * t / gl) + 0.08 * np.cos(4 * np.pi * t / gl)
+    elif win == 1:
+        g = 0.5 + 0.5 * np.cos(2 * np.pi * t / gl)
+    else:
+        raise ValueError(win)
+    return g / np.linalg.norm(g)
+
+
+def atom(d, m: int, n: int, L: int) -> np.ndarray:
+    """d_{m,n}(l) = g(l - n a) exp(2 pi i m (l - n a) / M), circular in l (Eq. gabdict)."""
+    win, gl, a, M = d
+    g = _window(win, gl)
+    out = np.zeros(L, np.complex128)
+    t = np.arange(-gl // 2, gl // 2)
+    l = (n * a + t) % L
+    ph = np.exp(2j * np.pi * ((m * t) % M) / M)
+    np.add.at(out, l, g * ph)
+    return out
+
+
+def dictionary(dicts, L: int):
+    """All reduced atoms as columns, in global index order p = off_w + n*(M_w/2+1) + m."""
+    cols, index = [], []
+    for w, d in enumerate(dicts):
+        a, M = d[2], d[3]
+        for n in range(L // a):
+            for m in range(M // 2 + 1):
+                cols.append(atom(d, m, n, L))
+                index.append((w, m, n))
+    return np.stack(cols, axis=1), index
+
+
+def mp(dicts, x: np.ndarray, n_iter: int, stop_rel: float = 0.0):
+    """Returns (w, m, n, c, E) with E[k] = ||r_{k+1}||^2 after each selection."""
+    x = np.asarray(x, np.float64)
+    L = len(x)
+    D, index = dictionary(dicts, L)
+    r = x.copy()
+    E0 = float(r @ r)
+    ws, ms, ns, cs, Es = [], [], [], [], []
+    for _ in range(n_iter):
+        rho = D.conj().T @ r
+        mag = rho.real ** 2 + rho.imag ** 2
+        p = int(np.argmax(mag))
+        w, m, n = index[p]
+        M = dicts[w][3]
+        d = D[:, p]
+        if m == 0 or 2 * m == M:
+            c = rho[p]
+            r = r - (c * d).real
+        else:
+            A = np.stack([d, d.conj()], axis=1)
+            sol, *_ = np.linalg.lstsq(A, r.astype(np.complex128), rcond=None)
+            c = sol[0]
+            r = r - (A @ sol).real
+        ws.append(w)
+        ms.append(m)
+        ns.append(n)
+        cs.append(c)
+        Es.append(float(r @ r))
+        if Es[-1] <= stop_rel * E0:
+            break
+    return (np.array(ws), np.array(ms), np.array(ns), np.array(cs), np.array(Es))

@@ -1,0 +1,400 @@
+"""Pins for the FP64 CPU oracle: each test ties the oracle to something other
+than itself - values printed in the paper, brute-force signal-domain inner
+products, library routines (numpy FFT / least squares), textbook MP, closed
+forms and the paper's invariants - so that a dropped term, wrong sign, wrong
+index or transposed operand in the oracle fails at least one of them."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import core as O
+from oracle import textbook as T
+from paper_2202_12380_amd import signals as S
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _cmod(v, n):
+    r = v % n
+    return r - n if r > n // 2 else r
+
+
+# --------------------------------------------------------------------------
+# P1: window shape, threshold semantics and kernel geometry (Fig. 1)
+
+def test_p1_fig1_kernel_boxes():
+    gold = json.load(open(os.path.join(GOLD, "fig1_kernel_boxes.json")))
+    a, M, gl = gold["a"], gold["M"], gold["gl"]
+    for name, win in (("blackman", O.WIN_BLACKMAN), ("hann", O.WIN_HANN)):
+        d = (win, gl, a, M)
+        t = O.kernel_table(d, d, gold["relative_threshold"], O.THR_REL)
+        assert [2 * t.box_mu + 1, 2 * t.box_delta + 1] == gold["boxes_mu_by_delta"][name]
+        # for an auto kernel the peak is ||g||^2 = 1, so absolute == relative
+        t2 = O.kernel_table(d, d, gold["relative_threshold"], 0)
+        assert (t2.box_mu, t2.box_delta) == (t.box_mu, t.box_delta)
+
+
+def test_p1_window_unit_norm_and_shape():
+    for win in (O.WIN_BLACKMAN, O.WIN_HANN):
+        for gl in (16, 256, 4096):
+            g = O.window(win, gl)
+            assert abs(np.sum(g * g) - 1.0) < 1e-14
+            # zero at t = -gl/2, maximum at t = 0, even about t = 0
+            assert abs(g[0]) < 1e-15
+            assert np.argmax(g) == gl // 2
+            assert np.allclose(g[1:], g[1:][::-1], atol=1e-16)
+    # Blackman coefficients 0.42 / 0.5 / 0.08 (before normalisation)
+    g = O.window(O.WIN_BLACKMAN, 64)
+    assert abs(g[64 // 2 + 16] / g[64 // 2] - (0.42 - 0.08) / 1.0) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# P2: kernels, modulation and phase convention vs brute-force inner products
+
+PAIR_CASES = [
+    ((0, 16, 4, 16), (0, 32, 8, 32)),
+    ((0, 32, 8, 32), (0, 16, 4, 16)),
+    ((0, 16, 4, 16), (0, 16, 4, 16)),
+    ((1, 32, 16, 32), (0, 16, 4, 16)),
+    ((0, 16, 8, 32), (0, 32, 8, 32)),   # gl < M
+]
+
+
+@pytest.mark.parametrize("dw,dv", PAIR_CASES)
+def test_p2_kernel_matches_bruteforce_gram(dw, dv):
+    L = 128
+    tab = O.kernel_table(dw, dv, 0.0)
+    rng = np.random.default_rng(1)
+    rv, rw = tab.Mmax // dv[3], tab.Mmax // dw[3]
+    picks = [(0, 0), (dv[3] // 2, 1)] + [(int(rng.integers(0, dv[3] // 2 + 1)),
+                                          int(rng.integers(0, L // dv[2]))) for _ in range(6)]
+    for k, j in picks:
+        dsel = T.atom(dv, k, j, L)
+        for _ in range(40):
+            m = int(rng.integers(0, dw[3] // 2 + 1))
+            n = int(rng.integers(0, L // dw[2]))
+            dt = T.atom(dw, m, n, L)
+            brute = np.vdot(dt, dsel)          # <d_sel, d_target> = sum d_sel conj(d_target)
+            Delta = _cmod(n * dw[2] - j * dv[2], L)
+            mu = (m * rw - k * rv) % tab.Mmax
+            if abs(Delta) > tab.D * tab.amin:
+                assert abs(brute) < 1e-15
+                continue
+            ph = np.exp(2j * np.pi * ((k * Delta) % dv[3]) / dv[3])
+            G = tab.h[Delta // tab.amin + tab.D, mu] * ph
+            assert abs(G - brute) < 1e-14, (k, j, m, n)
+            # the direct-sum entry agrees with the FFT-built table
+            hd = O.kernel_direct(dw, dv, mu, Delta)
+            assert abs(hd - tab.h[Delta // tab.amin + tab.D, mu]) < 1e-14
+
+
+def test_p2_threshold_is_elementwise_strict_absolute():
+    d = (0, 256, 64, 256)
+    full = O.kernel_table(d, d, 0.0)
+    for eps in (1e-5, 1e-4, 1e-3):
+        t = O.kernel_table(d, d, eps)
+        keep = np.abs(full.h) > eps
+        assert np.array_equal(t.h != 0, keep)
+        assert np.array_equal(t.h[keep], full.h[keep])
+    # relative threshold on a cross kernel scales with its peak (< 1)
+    dw, dv = (0, 256, 64, 256), (0, 4096, 1024, 4096)
+    fa = O.kernel_table(dw, dv, 0.0)
+    pk = np.abs(fa.h).max()
+    assert 0.2 < pk < 0.6
+    tr = O.kernel_table(dw, dv, 1e-4, O.THR_REL)
+    assert np.array_equal(tr.h != 0, np.abs(fa.h) > 1e-4 * pk)
+
+
+def test_p2_kernel_conjugate_symmetry():
+    # real even windows: h(-mu, -Delta) = conj(h(mu, Delta)) up to the phase of the
+    # twisted convolution; for the auto kernel, h(mu, 0) is real (gamma is real)
+    d = (0, 64, 16, 64)
+    t = O.kernel_table(d, d, 0.0)
+    assert np.max(np.abs(t.h[t.D].imag)) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# P3: DGT
+
+@pytest.mark.parametrize("d", [(0, 16, 4, 16), (0, 32, 8, 64), (1, 64, 16, 64)])
+def test_p3_dgt_direct_fft_numpy(d):
+    L = 256
+    x = np.random.default_rng(2).standard_normal(L)
+    c1 = O.dgt(d, x)
+    c2 = O.dgt(d, x, direct=True)
+    assert np.max(np.abs(c1 - c2)) < 1e-12
+    # numpy FFT of the circularly laid out windowed frame
+    win, gl, a, M = d
+    g = O.window(win, gl)
+    t = np.arange(-gl // 2, gl // 2)
+    for n in range(L // a):
+        buf = np.zeros(M)
+        buf[t % M] = x[(n * a + t) % L] * g
+        ref = np.fft.fft(buf)[: M // 2 + 1]
+        assert np.max(np.abs(ref - c1[n])) < 1e-12
+    # and the brute-force dictionary
+    D, _ = T.dictionary([d], L)
+    assert np.max(np.abs(D.conj().T @ x - c1.ravel())) < 1e-12
+
+
+def test_p3_fft_against_direct_dft():
+    for n in (1, 2, 8, 64, 1024):
+        x = np.random.default_rng(n).standard_normal(n) + 1j * np.random.default_rng(n + 1).standard_normal(n)
+        X = O.fft(x)
+        k = np.arange(n)
+        ref = np.exp(-2j * np.pi * np.outer(k, k) / n) @ x
+        assert np.max(np.abs(X - ref)) < 1e-11 * max(1, n)
+        assert np.max(np.abs(O.fft(X, +1) / n - x)) < 1e-12
+
+
+def test_p3_planted_atom_column():
+    # x = Re(alpha d_{m0,n0}) has rho_0 = (alpha G(., p0) + conj(alpha) G(., conj p0)) / 2
+    dicts = [(0, 32, 8, 32), (0, 64, 16, 64)]
+    L = 256
+    m0, n0, alpha = 5, 7, 0.7 - 1.3j
+    x = (alpha * T.atom(dicts[0], m0, n0, L)).real
+    for w, d in enumerate(dicts):
+        tab = O.kernel_table(d, dicts[0], 0.0)
+        rw, rv = tab.Mmax // d[3], tab.Mmax // dicts[0][3]
+        plane = O.dgt(d, x)
+        for n in range(L // d[2]):
+            Delta = _cmod(n * d[2] - n0 * dicts[0][2], L)
+            for m in range(d[3] // 2 + 1):
+                exp_ = 0j
+                if abs(Delta) <= tab.D * tab.amin:
+                    col = Delta // tab.amin + tab.D
+                    ph = np.exp(2j * np.pi * ((m0 * Delta) % dicts[0][3]) / dicts[0][3])
+                    G1 = tab.h[col, (m * rw - m0 * rv) % tab.Mmax] * ph
+                    G2 = tab.h[col, (m * rw + m0 * rv) % tab.Mmax] * np.conj(ph)
+                    exp_ = (alpha * G1 + np.conj(alpha) * G2) / 2
+                assert abs(plane[n, m] - exp_) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# P4: real-atom pair coefficient and energy decrease
+
+def test_p4_pair_coefficient_and_energy_vs_lstsq():
+    dicts = [(0, 32, 8, 32)]
+    L = 128
+    rng = np.random.default_rng(3)
+    for trial in range(6):
+        x = rng.standard_normal(L)
+        # plant a strong low-frequency pair so that gamma != 0 is exercised
+        m0 = [1, 2, 15, 14, 3, 1][trial]
+        x += 5 * (np.exp(1j * trial) * T.atom(dicts[0], m0, 3 + trial, L)).real
+        r = O.mp(dicts, x, 0.0, K=1)
+        w, m, n, c = int(r.w[0]), int(r.m[0]), int(r.n[0]), r.c[0]
+        d = T.atom(dicts[0], m, n, L)
+        if m == 0 or 2 * m == dicts[0][3]:
+            cref = np.vdot(d, x)
+            u = (cref * d).real
+        else:
+            A = np.stack([d, d.conj()], axis=1)
+            sol, *_ = np.linalg.lstsq(A, x.astype(complex), rcond=None)
+            cref = sol[0]
+            u = (A @ sol).real
+            gamma = np.sum(d * d)
+            if m in (1, 2, 14, 15):
+                assert abs(gamma) > 1e-6
+        assert abs(c - cref) < 1e-12 * abs(cref)
+        Et = r.E0 - r.E[0]
+        assert abs(Et - (x @ x - (x - u) @ (x - u))) < 1e-12 * (x @ x)
+
+
+# --------------------------------------------------------------------------
+# P5: MP loop at eps = 0 equals textbook MP
+
+P5_CASES = [
+    ([(0, 16, 4, 16)], 64, 0),
+    ([(0, 16, 4, 16), (0, 32, 8, 32)], 128, 1),
+    ([(0, 32, 8, 32), (0, 16, 4, 16)], 128, 2),
+    ([(1, 32, 8, 64), (0, 64, 16, 64)], 256, 3),
+    ([(0, 32, 16, 32), (0, 64, 16, 64)], 256, 4),
+    ([(0, 64, 16, 64), (0, 128, 32, 128)], 1024, 5),
+]
+
+
+@pytest.mark.parametrize("dicts,L,seed", P5_CASES)
+def test_p5_eps0_equals_textbook(dicts, L, seed):
+    x = np.random.default_rng(seed).standard_normal(L)
+    n_it = 120 if L <= 256 else 60
+    r = O.mp(dicts, x, 0.0, K=n_it)
+    w, m, n, c, E = T.mp(dicts, x, n_it)
+    k = min(r.n_atoms, len(w))
+    assert k == n_it
+    assert np.array_equal(r.w[:k], w[:k])
+    assert np.array_equal(r.m[:k], m[:k])
+    assert np.array_equal(r.n[:k], n[:k])
+    assert np.max(np.abs(r.c[:k] - c[:k]) / np.abs(c[:k])) < 1e-11
+    assert np.max(np.abs(r.E[:k] - E[:k])) < 1e-12 * r.E0
+
+
+# --------------------------------------------------------------------------
+# P6: invariants at eps > 0
+
+def _gamma(dv, k, eps):
+    t = O.kernel_table(dv, dv, eps)
+    return t.h[t.D, (-2 * k) % t.Mmax]
+
+
+def test_p6_energy_identity_and_orthogonality():
+    dicts = [(0, 64, 16, 64), (0, 128, 32, 128)]
+    L = 1024
+    eps = 1e-3
+    x = np.random.default_rng(11).standard_normal(L)
+    r = O.mp(dicts, x, eps, K=200, return_planes=True)
+    E = np.concatenate([[r.E0], r.E])
+    for i in range(r.n_atoms):
+        M = dicts[r.w[i]][3]
+        c = r.c[i]
+        if r.m[i] == 0 or 2 * r.m[i] == M:
+            Et = abs(c) ** 2
+        else:
+            g = _gamma(dicts[r.w[i]], int(r.m[i]), eps)
+            Et = 2 * (c.real ** 2 + c.imag ** 2 + g.real * (c.real ** 2 - c.imag ** 2)
+                      - 2 * g.imag * c.real * c.imag)
+        assert abs((E[i] - E[i + 1]) - Et) <= 1e-15 * r.E0
+    # the last selected coefficient is annihilated by its own update
+    for K in (1, 2, 17, 50):
+        rk = O.mp(dicts, x, eps, K=K - 1, return_planes=True) if K > 1 else None
+        before = rk.planes if rk is not None else [O.dgt(d, x) for d in dicts]
+        after = O.mp(dicts, x, eps, K=K, return_planes=True)
+        w, m, n = int(after.w[-1]), int(after.m[-1]), int(after.n[-1])
+        assert abs(after.planes[w][n, m]) <= 1e-14 * abs(before[w][n, m])
+
+
+def test_p6_theorem1_bound():
+    # |<r_k, d_p> - rho_k(p)| <= eps * sum_l (1 + pair_l) |c_l| for all p (proof of Thm. 1)
+    dicts = [(0, 64, 16, 64), (0, 256, 64, 256)]
+    L = 2048
+    x = np.random.default_rng(12).standard_normal(L)
+    for eps in (1e-3, 1e-2):
+        for K in (10, 100, 300):
+            r = O.mp(dicts, x, eps, K=K, return_planes=True)
+            y = O.resynth(dicts, r.L_padded, r.w, r.m, r.n, r.c)
+            res = x - y
+            pair = np.array([0 if (m == 0 or 2 * m == dicts[w][3]) else 1
+                             for w, m in zip(r.w, r.m)])
+            bound = eps * np.sum((1 + pair) * np.abs(r.c))
+            worst = 0.0
+            for w, d in enumerate(dicts):
+                true = O.dgt(d, res)
+                worst = max(worst, np.max(np.abs(true - r.planes[w])))
+            assert worst <= bound * (1 + 1e-9) + 1e-12
+            assert worst > 0.0
+
+
+def test_p6_sequences_converge_as_eps_shrinks():
+    dicts = [(0, 64, 16, 64), (0, 128, 32, 128)]
+    x = np.random.default_rng(13).standard_normal(1024)
+    ref = O.mp(dicts, x, 0.0, K=300)
+    agree = []
+    for eps in (1e-2, 1e-4, 1e-6, 1e-9):
+        r = O.mp(dicts, x, eps, K=300)
+        same = (r.w == ref.w) & (r.m == ref.m) & (r.n == ref.n)
+        agree.append(int(np.argmin(same)) if not same.all() else len(same))
+    assert agree == sorted(agree)
+    assert agree[-1] == 300 and agree[0] < 300
+
+
+# --------------------------------------------------------------------------
+# P7: convergence vs threshold on white noise (Sec. 6.1, Fig. 4) - monotone;
+# the exact counts are parity unpinned (Matlab's noise samples are unavailable)
+
+def test_p7_convergence_vs_threshold_monotone():
+    gold = json.load(open(os.path.join(GOLD, "fig4_noise_convergence.json")))
+    dicts = [(0, M, M // 4, M) for M in (512, 1024, 2048)]
+    L = 1 << 14
+    x = np.random.default_rng(7).standard_normal(L)
+    steps, snrs = [], []
+    for run in gold["runs"]:
+        r = O.mp(dicts, x, run["eps"], K=20 * L, cap=20 * L)
+        assert r.stop_reason == O.STOP_ENEG
+        y = O.resynth(dicts, r.L_padded, r.w, r.m, r.n, r.c)
+        steps.append(r.n_atoms)
+        snrs.append(10 * np.log10(r.E0 / np.sum((x - y) ** 2)))
+    assert steps == sorted(steps, reverse=True)
+    assert snrs == sorted(snrs, reverse=True)
+    # same regime as the paper at 1e-4: about one selection per sample, > 50 dB
+    assert 0.8 * L < steps[0] < 1.5 * L and snrs[0] > 50
+
+
+# --------------------------------------------------------------------------
+# P8: planted atoms with disjoint supports are recovered exactly for any eps
+
+@pytest.mark.parametrize("eps", [0.0, 1e-4, 1e-2])
+def test_p8_planted_disjoint_atoms(eps):
+    gl, a, M = 512, 128, 512
+    L = 16384
+    g = np.random.default_rng(21)
+    frames = g.permutation(np.arange(0, L // a, 4))[:32]   # >= gl/a apart
+    x = np.zeros(L)
+    planted = []
+    for n in frames:
+        m = int(g.integers(3, M // 2 - 2))
+        alpha = complex(g.standard_normal(), g.standard_normal())
+        S.add_atom(x, gl, a, M, m, int(n), alpha)
+        planted.append((abs(alpha), m, int(n), alpha))
+    planted.sort(key=lambda t: -t[0])
+    r = O.mp([(0, gl, a, M)], x, eps, K=32)
+    assert r.n_atoms == 32
+    for i, (_, m, n, alpha) in enumerate(planted):
+        assert (r.m[i], r.n[i]) == (m, n)
+        assert abs(r.c[i] - alpha / 2) < 1e-12 * abs(alpha)
+    # the estimate is left with subtraction rounding only; the true residual is ~0
+    assert abs(r.E[-1]) < 1e-13 * r.E0
+    y = O.resynth([(0, gl, a, M)], L, r.w, r.m, r.n, r.c)
+    assert np.sum((x - y) ** 2) < 1e-24 * r.E0
+
+
+# --------------------------------------------------------------------------
+# stop rules and argument checks
+
+def test_stop_rules_and_errors():
+    dicts = [(0, 64, 16, 64)]
+    x = np.random.default_rng(5).standard_normal(512)
+    r = O.mp(dicts, x, 1e-4, K=7)
+    assert r.n_atoms == 7 and r.stop_reason == O.STOP_K
+    r = O.mp(dicts, x, 1e-4, K=10000, cap=10000, target_db=10.0)
+    assert r.stop_reason == O.STOP_SNR
+    assert r.E[-1] <= r.E0 * 0.1 < r.E[-2]
+    r = O.mp(dicts, np.zeros(512), 1e-4, K=10)
+    assert r.n_atoms == 0 and r.stop_reason == O.STOP_ZERO
+    r = O.mp(dicts, x, 5e-2, K=100000, cap=100000)
+    assert r.stop_reason == O.STOP_ENEG and r.E[-1] < 0 <= r.E[-2]
+    # default K = L/5
+    r = O.mp(dicts, x, 1e-4)
+    assert r.n_atoms == 512 // 5
+    # grids
+    assert O.check_dicts([(0, 64, 16, 64), (0, 64, 24, 96)]) != 0     # M not power of 2
+    assert O.check_dicts([(0, 64, 16, 64), (0, 128, 48, 128)]) != 0   # a not nested
+    assert O.check_dicts([(0, 128, 16, 64)]) != 0                     # gl > M
+    assert O.check_dicts([(0, 64, 48, 64)]) != 0                      # M/a not integer
+    assert O.padded_length([(0, 64, 16, 64)], 100) == 128
+    assert O.padded_length([(0, 256, 64, 256), (0, 4096, 1024, 4096)], 441000) == 442368
+    assert O.padded_length([(0, 64, 16, 64)], 64) < 0                 # shorter than 2 gl
+
+
+def test_padding_is_zero_extension():
+    dicts = [(0, 64, 16, 64)]
+    x = np.random.default_rng(6).standard_normal(500)
+    r1 = O.mp(dicts, x, 1e-4, K=40)
+    r2 = O.mp(dicts, np.concatenate([x, np.zeros(12)]), 1e-4, K=40)
+    assert r1.L_padded == 512
+    assert np.array_equal(r1.w, r2.w) and np.array_equal(r1.m, r2.m)
+    assert np.array_equal(r1.n, r2.n) and np.array_equal(r1.c, r2.c)
+
+
+def test_resynth_matches_dictionary():
+    dicts = [(0, 32, 8, 32), (0, 64, 16, 64)]
+    L = 256
+    x = np.random.default_rng(9).standard_normal(L)
+    r = O.mp(dicts, x, 1e-4, K=30)
+    y = O.resynth(dicts, L, r.w, r.m, r.n, r.c)
+    ref = np.zeros(L)
+    for w, m, n, c in zip(r.w, r.m, r.n, r.c):
+        d = T.atom(dicts[w], int(m), int(n), L)
+        ref += (c * d + (np.conj(c) * d.conj() if (m != 0 and 2 * m != dicts[w][3]) else 0)).real
+    assert np.max(np.abs(y - ref)) < 1e-13
