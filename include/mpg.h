@@ -1,0 +1,197 @@
+/*
+ * mpg.h - C-ABI of the MI355X matching-pursuit library (libmpg.so).
+ *
+ * The library computes approximate coefficient-domain matching pursuit (MP)
+ * on multi-Gabor dictionaries for batches of real signals, after
+ * Prusa, Holighaus, Balazs, "Fast Matching Pursuit with Multi-Gabor
+ * Dictionaries", ACM TOMS 47(3), 2021:
+ *   - DGT analysis rho_0 = D* x in every Gabor system (Sec. 5);
+ *   - per iteration: the global maximum of |rho|^2 taken from a max tree
+ *     (Sec. 5.1), the real-atom pair adjustment (Sec. 5, Eqs. dualatprod and
+ *     projenfaster), and the residual update by truncated, modulated
+ *     cross-kernels (Sec. 4, Eqs. GramKern, hkj, fastkernupdate; Alg. 3);
+ *   - synthesis of the selected atoms (Sec. 5, Eq. idgtreal).
+ *
+ * Conventions.
+ *   - Every function returns 0 (MP_OK) or a negative MP_E_* code and never
+ *     throws.  On error the plan is left unchanged.
+ *   - "_dev" pointers are device pointers owned by the caller; "_host"
+ *     pointers are host memory owned by the caller.  The plan owns every
+ *     buffer it allocates and frees them in mp_plan_destroy.
+ *   - Calls taking a hipStream_t only enqueue work on that stream (they may
+ *     block only in mp_plan_create).  mp_get_atoms, mp_get_energy and
+ *     mp_get_stats wait for the stream of the last mp_run on the plan.
+ *   - Calls on one plan must not overlap; different plans are independent.
+ *   - Signal s of a batch is identified by its index 0 .. batch-1.
+ *   - Coefficient planes are laid out N_w x (M_w/2 + 1), bin m fastest
+ *     (c(m, n) = c[n * (M_w/2 + 1) + m]), interleaved complex.
+ */
+#ifndef MPG_H
+#define MPG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define MP_OK 0
+#define MP_E_ARG (-1)   /* invalid argument (null pointer, bad size, bad index) */
+#define MP_E_GRID (-2)  /* systems not compatible: a or M not nested, M/a not integer,
+                           M not a power of two, gl odd or gl > M (Sec. 2.1)      */
+#define MP_E_LEN (-3)   /* a padded length is shorter than gl_v + gl_w of some pair  */
+#define MP_E_NOMEM (-4) /* device or host allocation failed                         */
+#define MP_E_HIP (-5)   /* a HIP runtime call failed                                */
+#define MP_E_STATE (-6) /* call out of order (e.g. mp_run before mp_analyze)        */
+#define MP_E_LIMIT (-7) /* a size exceeds a limit of this implementation            */
+
+/* ---- windows ---- */
+#define MP_WIN_BLACKMAN 0
+#define MP_WIN_HANN 1
+
+/* ---- plan flags ---- */
+#define MP_PREC_F32 0x0u         /* FP32 planes, kernels and updates (default)      */
+#define MP_PREC_F64 0x1u         /* FP64 planes, kernels and updates               */
+#define MP_THR_REL 0x10u         /* threshold relative to each kernel's peak |h|   */
+#define MP_CONJ_GATE_GAMMA 0x20u /* conjugate-partner update only when gamma != 0  */
+
+/* ---- input sample types for mp_analyze / output types for mp_resynth ---- */
+#define MP_DTYPE_F32 0
+#define MP_DTYPE_F64 1
+
+/* ---- stop reasons (mp_signal_info.stop_reason) ---- */
+#define MP_STOP_NONE 0 /* not run yet                                  */
+#define MP_STOP_K 1    /* selection cap reached                        */
+#define MP_STOP_SNR 2  /* error estimate reached the target            */
+#define MP_STOP_ENEG 3 /* error estimate became negative (Sec. 6.1)    */
+#define MP_STOP_ZERO 4 /* all coefficients are zero                    */
+
+typedef struct mp_plan mp_plan;
+
+/* One Gabor system (g, a, M): window shape, window length gl, hop a and
+ * number of channels M (Sec. 2.1, Eq. gabdict). */
+typedef struct {
+  int32_t window, gl, a, M;
+} mp_dict;
+
+/* One selected real atom: system w, bin m (0..M_w/2), frame n, the adjusted
+ * coefficient c~ of Eq. (dualatprod), and the error estimate E_k after the
+ * selection (Alg. 1, error update, with Eq. projenfaster). */
+typedef struct {
+  int32_t w, m, n, pad;
+  double re, im;
+  double E_after;
+} mp_atom;
+
+typedef struct {
+  int64_t L;           /* length given at plan creation                       */
+  int64_t L_padded;    /* zero-padded length (multiple of lcm(a_w, M_w))       */
+  int64_t x_offset;    /* element offset of this signal in the packed input   */
+  int64_t n_coefs;     /* sum_w N_w (M_w/2 + 1)                                */
+  int64_t n_atoms;     /* selections made so far                              */
+  int32_t stop_reason; /* MP_STOP_*                                           */
+  int32_t pad;
+  double E0;           /* ||x||^2                                             */
+  double E;            /* current error estimate                              */
+} mp_signal_info;
+
+typedef struct {
+  int32_t amin, Mmax;     /* common grid of the pair (Sec. 4.2)              */
+  int32_t D;              /* largest |delta| whose supports overlap         */
+  int32_t delta_box;      /* half extent in delta of the surviving entries  */
+  int32_t mu_lo, mu_hi;   /* extent in mu of the surviving entries          */
+  int64_t n_nonzero;      /* surviving entries |h| > threshold              */
+} mp_kernel_info;
+
+typedef struct {
+  int64_t atoms;          /* selections in the last mp_run, over the batch  */
+  int64_t updated;        /* coefficient updates with a nonzero kernel entry */
+  int64_t blocks;         /* 64-coefficient blocks read and rescanned       */
+  int64_t l1_groups;      /* tree groups recomputed                          */
+  double loop_ms;         /* device time of the last mp_run's MP kernel     */
+  double analyze_ms;      /* device time of the last mp_analyze             */
+  double dgt_ms;          /* device time of the DGT kernels in it           */
+} mp_stats;
+
+/* Creates a plan for `batch` signals of lengths L[0..batch-1] and the W
+ * Gabor systems dicts[0..W-1].  Validates the grids (Sec. 2.1), pads each
+ * length to a multiple of lcm(a_w, M_w), and precomputes on the device, in
+ * FP64, every truncated cross-kernel h_{w,v} on its common grid (Sec. 4.1,
+ * 4.2; threshold Eq. truncgram, absolute unless MP_THR_REL) plus FP32 copies.
+ * kernel_tol is the threshold epsilon (> 0).  flags: MP_PREC_*, MP_THR_REL,
+ * MP_CONJ_GATE_GAMMA.  Uses the current HIP device; blocks until the
+ * kernels are built.  *out receives the plan. */
+int mp_plan_create(const mp_dict *dicts, int32_t W, const int64_t *L,
+                   int32_t batch, double kernel_tol, uint32_t flags,
+                   mp_plan **out);
+
+/* Analysis: E0 = ||x||^2 (FP64), rho_0 = D_w* x for every system (Sec. 5)
+ * and the max tree over |rho_0|^2 (Sec. 5.1).  x_dev holds the batch packed
+ * back to back in the order given at creation (signal s starts at element
+ * sum_{r<s} L[r]); dtype is MP_DTYPE_F32 or MP_DTYPE_F64.  Resets the atom
+ * logs. */
+int mp_analyze(mp_plan *plan, const void *x_dev, int32_t dtype,
+               hipStream_t stream);
+
+/* Runs the MP loop of every signal until a stop rule holds: n_atoms >=
+ * max_atoms (<= 0: L_padded/5 per signal), E <= 10^(-target_snr_db/10) E0
+ * (target_snr_db <= 0: no SNR rule), E < 0, or max |rho| = 0 (Alg. 1 with
+ * the stopping conditions of Sec. 6.1 and Sec. 7).  Continues from the
+ * current state when called again without mp_analyze. */
+int mp_run(mp_plan *plan, int64_t max_atoms, double target_snr_db,
+           hipStream_t stream);
+
+/* Copies up to `cap` selected atoms of signal `sig` to out_host, in
+ * selection order; *n_out receives the number of atoms selected. */
+int mp_get_atoms(const mp_plan *plan, int32_t sig, mp_atom *out_host,
+                 int64_t cap, int64_t *n_out);
+
+/* Error-estimate curve of signal `sig`: E_0 followed by E_k after each
+ * selection; *n_out receives n_atoms + 1. */
+int mp_get_energy(const mp_plan *plan, int32_t sig, double *E_curve_host,
+                  int64_t cap, int64_t *n_out);
+
+/* Solution vector of signal `sig` in system w: the sum of c~ of the
+ * selected atoms at each (m, n) (Alg. 1, solution update), as FP64 complex
+ * N_w x (M_w/2 + 1) into c_dev. */
+int mp_get_coefs(const mp_plan *plan, int32_t sig, int32_t w, void *c_dev,
+                 hipStream_t stream);
+
+/* Current residual coefficient plane of signal `sig` in system w
+ * (coefficient-domain residual rho), N_w x (M_w/2 + 1) complex in the plan's
+ * precision (FP32 pairs or FP64 pairs) into dst_dev. */
+int mp_get_residual(const mp_plan *plan, int32_t sig, int32_t w,
+                    void *dst_dev, hipStream_t stream);
+
+/* Synthesis of the selected atoms of signal `sig` (Eq. idgtreal): pairs add
+ * 2 Re(c d), DC and Nyquist atoms add Re(c d).  y_dev receives L_padded
+ * samples of type dtype (MP_DTYPE_F32 or MP_DTYPE_F64); accumulation is
+ * FP64. */
+int mp_resynth(const mp_plan *plan, int32_t sig, void *y_dev, int32_t dtype,
+               hipStream_t stream);
+
+int mp_signal_info_get(const mp_plan *plan, int32_t sig, mp_signal_info *out);
+
+/* Pair (target w, source v) kernel geometry, and the FP64 box table
+ * h_{w,v}(mu, delta) for delta = -delta_box..delta_box (rows) and
+ * mu = mu_lo..mu_hi (columns, fastest): (2 delta_box + 1)(mu_hi - mu_lo + 1)
+ * complex values as separate re / im host arrays, entries at or below the
+ * threshold set to zero. */
+int mp_kernel_info_get(const mp_plan *plan, int32_t w, int32_t v,
+                       mp_kernel_info *out);
+int mp_get_kernel(const mp_plan *plan, int32_t w, int32_t v, double *re_host,
+                  double *im_host, int64_t cap);
+
+/* Counters and device timings of the last mp_analyze / mp_run. */
+int mp_get_stats(const mp_plan *plan, mp_stats *out);
+
+int mp_plan_destroy(mp_plan *plan);
+
+const char *mp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,799 @@
+// Host side of libmpg: plan validation and layout, FP64 kernel precompute
+// driver, and the C-ABI entry points declared in include/mpg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "mpg.h"
+#include "mpg_internal.h"
+
+namespace mpg {
+
+hipError_t launch_roots(int M, int n, int sign, double2* o64, float2* o32, hipStream_t st);
+hipError_t launch_gram_full(const double* gw, int glw, const double* gv, int glv, int amin, int D,
+                            int Mmax, const double2* roots, double2* out, hipStream_t st);
+hipError_t launch_gram_absmax(const double2* t, int64_t n, unsigned long long* out, hipStream_t st);
+hipError_t launch_gram_box(const double2* t, int D, int Mmax, double thr, int* box, hipStream_t st);
+hipError_t launch_gram_extract(const double2* t, int D, int Mmax, double thr, int dbox, int mu_lo,
+                               int width, double2* o64, float2* o32, hipStream_t st);
+hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch, SigState* st_,
+                         hipStream_t st);
+hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
+                      int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
+                      const void* win, const void* tw, void* planes, hipStream_t st);
+hipError_t launch_leaves(bool f64, const void* planes, void* leaves, const SigDev* sigs, int batch, int W,
+                         const DictDev* dicts, int64_t total_blocks, hipStream_t st);
+size_t leaf_bytes(bool f64);
+hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, size_t shmem, hipStream_t st);
+hipError_t launch_resynth(const AtomRec* atoms, const SigState* st_, const DictDev* dicts,
+                          const double* win64, int64_t Lp, double* acc, void* y, int dtype,
+                          hipStream_t st);
+hipError_t launch_coefs(const AtomRec* atoms, const SigState* st_, int w, int MR, int64_t n_entries,
+                        void* c, hipStream_t st);
+}  // namespace mpg
+
+using namespace mpg;
+
+struct mp_plan {
+  int device = 0;
+  int W = 0, batch = 0;
+  uint32_t flags = 0;
+  double eps = 0.0;
+  bool f64 = false;
+  std::vector<mp_dict> dicts;
+  std::vector<DictDev> hd;
+  std::vector<PairDev> hp;
+  std::vector<SigDev> hs;
+  std::vector<mp_kernel_info> kinfo;
+  std::vector<std::vector<double>> kre, kim;
+  std::vector<int32_t> order;
+  std::vector<int64_t> frames_total;  // per system, over the batch
+  int G = 64, logG = 6, n_groups_max = 0;
+  int nt = 512, grid = 1;
+  size_t shmem = 0;
+  int64_t total_coef = 0, total_leaves = 0, total_cap = 0, max_Lp = 0;
+  bool analyzed = false;
+  hipStream_t last_stream = nullptr;
+  int64_t last_K = 0;
+
+  // device memory
+  DictDev* d_dicts = nullptr;
+  PairDev* d_pairs = nullptr;
+  SigDev* d_sigs = nullptr;
+  SigState* d_state = nullptr;
+  double* d_win64 = nullptr;
+  float* d_win32 = nullptr;
+  double2* d_tw64 = nullptr;
+  float2* d_tw32 = nullptr;
+  double2* d_tab64 = nullptr;
+  float2* d_tab32 = nullptr;
+  double2* d_gam64 = nullptr;
+  float2* d_gam32 = nullptr;
+  void* d_planes = nullptr;
+  void* d_leaves = nullptr;
+  AtomRec* d_atoms = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_queue = nullptr;
+  int64_t* d_fprefix[MAXW] = {};
+  double* d_acc = nullptr;
+  hipEvent_t ev[6] = {};
+  bool ev_valid = false;
+  bool ran = false;
+};
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+// Centred periodic window on t = -gl/2 .. gl/2-1, unit 2-norm (Sec. 2.1).
+void make_window(int type, int gl, std::vector<double>& g) {
+  g.resize(gl);
+  const double pi = 3.14159265358979323846;
+  double e = 0.0;
+  for (int i = 0; i < gl; ++i) {
+    const double t = (double)(i - gl / 2);
+    double v = type == MP_WIN_BLACKMAN
+                   ? 0.42 + 0.5 * std::cos(2.0 * pi * t / gl) + 0.08 * std::cos(4.0 * pi * t / gl)
+                   : 0.5 + 0.5 * std::cos(2.0 * pi * t / gl);
+    g[i] = v;
+    e += v * v;
+  }
+  const double s = 1.0 / std::sqrt(e);
+  for (auto& v : g) v *= s;
+}
+
+void free_plan(mp_plan* p) {
+  if (!p) return;
+  hipFree(p->d_dicts);
+  hipFree(p->d_pairs);
+  hipFree(p->d_sigs);
+  hipFree(p->d_state);
+  hipFree(p->d_win64);
+  hipFree(p->d_win32);
+  hipFree(p->d_tw64);
+  hipFree(p->d_tw32);
+  hipFree(p->d_tab64);
+  hipFree(p->d_tab32);
+  hipFree(p->d_gam64);
+  hipFree(p->d_gam32);
+  hipFree(p->d_planes);
+  hipFree(p->d_leaves);
+  hipFree(p->d_atoms);
+  hipFree(p->d_order);
+  hipFree(p->d_queue);
+  for (auto& f : p->d_fprefix) hipFree(f);
+  hipFree(p->d_acc);
+  if (p->ev_valid)
+    for (auto& e : p->ev) hipEventDestroy(e);
+  delete p;
+}
+
+int check_dicts(const mp_dict* d, int W) {
+  for (int w = 0; w < W; ++w) {
+    if (d[w].window != MP_WIN_BLACKMAN && d[w].window != MP_WIN_HANN) return MP_E_ARG;
+    if (d[w].gl <= 0 || d[w].a <= 0 || d[w].M <= 0) return MP_E_ARG;
+    if (!is_pow2(d[w].M) || d[w].M < 2) return MP_E_GRID;
+    if ((d[w].gl & 1) || d[w].gl > d[w].M) return MP_E_GRID;
+    if (d[w].M % d[w].a) return MP_E_GRID;
+  }
+  for (int w = 0; w < W; ++w)
+    for (int v = 0; v < W; ++v) {
+      const int amin = std::min(d[w].a, d[v].a), amax = std::max(d[w].a, d[v].a);
+      const int mmin = std::min(d[w].M, d[v].M), mmax = std::max(d[w].M, d[v].M);
+      if (amax % amin || mmax % mmin) return MP_E_GRID;
+    }
+  return MP_OK;
+}
+
+#define HCHK(x)                 \
+  do {                          \
+    if ((x) != hipSuccess) {    \
+      rc = MP_E_HIP;            \
+      goto fail;                \
+    }                           \
+  } while (0)
+
+#define ACHK(x)                                            \
+  do {                                                     \
+    hipError_t e_ = (x);                                   \
+    if (e_ != hipSuccess) {                                \
+      rc = e_ == hipErrorOutOfMemory ? MP_E_NOMEM : MP_E_HIP; \
+      goto fail;                                           \
+    }                                                      \
+  } while (0)
+
+// Grows the atom logs so that every signal can hold `need` atoms, keeping
+// what is already logged.
+int ensure_cap(mp_plan* p, int64_t K, hipStream_t st) {
+  std::vector<int64_t> caps(p->batch);
+  bool grow = false;
+  for (int s = 0; s < p->batch; ++s) {
+    const int64_t want = K > 0 ? K : std::max<int64_t>(p->hs[s].Lp / 5, 1);
+    caps[s] = std::max(p->hs[s].cap, want);
+    if (caps[s] != p->hs[s].cap) grow = true;
+  }
+  if (!grow) return MP_OK;
+  int64_t total = 0;
+  for (auto c : caps) total += c;
+  AtomRec* na = nullptr;
+  if (hipMalloc((void**)&na, sizeof(AtomRec) * (size_t)total) != hipSuccess) return MP_E_NOMEM;
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    hipFree(na);
+    return MP_E_HIP;
+  }
+  int64_t base = 0;
+  std::vector<SigDev> ns = p->hs;
+  for (int s = 0; s < p->batch; ++s) {
+    if (p->hs[s].cap > 0 &&
+        hipMemcpy(na + base, p->d_atoms + p->hs[s].atom_base, sizeof(AtomRec) * (size_t)p->hs[s].cap,
+                  hipMemcpyDeviceToDevice) != hipSuccess) {
+      hipFree(na);
+      return MP_E_HIP;
+    }
+    ns[s].atom_base = base;
+    ns[s].cap = caps[s];
+    base += caps[s];
+  }
+  if (hipMemcpy(p->d_sigs, ns.data(), sizeof(SigDev) * ns.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(na);
+    return MP_E_HIP;
+  }
+  hipFree(p->d_atoms);
+  p->d_atoms = na;
+  p->hs = ns;
+  p->total_cap = total;
+  return MP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mp_strerror(int code) {
+  switch (code) {
+    case MP_OK: return "ok";
+    case MP_E_ARG: return "invalid argument";
+    case MP_E_GRID: return "incompatible Gabor systems (a or M not nested, M/a not integer, M not a power of two, gl odd or gl > M)";
+    case MP_E_LEN: return "signal length too short for the kernels (padded L < gl_v + gl_w)";
+    case MP_E_NOMEM: return "out of memory";
+    case MP_E_HIP: return "HIP runtime error";
+    case MP_E_STATE: return "call out of order";
+    case MP_E_LIMIT: return "size exceeds an implementation limit";
+    default: return "unknown error";
+  }
+}
+
+int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t batch, double kernel_tol,
+                   uint32_t flags, mp_plan** out) {
+  if (!out) return MP_E_ARG;
+  *out = nullptr;
+  if (!dicts || !L || W < 1 || W > MAXW || batch < 1 || batch > (1 << 20)) return MP_E_ARG;
+  if (!(kernel_tol >= 0.0 && kernel_tol < 1.0)) return MP_E_ARG;
+  if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA)) return MP_E_ARG;
+  int rc = check_dicts(dicts, W);
+  if (rc) return rc;
+  for (int s = 0; s < batch; ++s)
+    if (L[s] <= 0) return MP_E_ARG;
+  {
+    // padded lengths must fit every pair's kernel (checked before any HIP call)
+    int64_t q = 1, need = 0;
+    for (int w = 0; w < W; ++w) {
+      q = q / gcd64(q, dicts[w].a) * dicts[w].a;
+      q = q / gcd64(q, dicts[w].M) * dicts[w].M;
+      for (int v = 0; v < W; ++v) need = std::max<int64_t>(need, dicts[w].gl + dicts[v].gl);
+    }
+    for (int s = 0; s < batch; ++s) {
+      const int64_t Lp = (L[s] + q - 1) / q * q;
+      if (Lp < need) return MP_E_LEN;
+      if (Lp >= (int64_t)1 << 30) return MP_E_LIMIT;
+    }
+  }
+
+  mp_plan* p = new (std::nothrow) mp_plan;
+  if (!p) return MP_E_NOMEM;
+  p->W = W;
+  p->batch = batch;
+  p->flags = flags;
+  p->eps = kernel_tol;
+  p->f64 = (flags & MP_PREC_F64) != 0;
+  p->dicts.assign(dicts, dicts + W);
+  hipStream_t st = nullptr;
+  double2* d_roots = nullptr;
+  double2* d_full = nullptr;
+  int* d_box = nullptr;
+  unsigned long long* d_max = nullptr;
+  std::vector<double2*> ptab64;
+  std::vector<float2*> ptab32;
+  {
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) {
+      delete p;
+      return MP_E_HIP;
+    }
+    HCHK(hipGetDevice(&p->device));
+    hipDeviceProp_t prop;
+    HCHK(hipGetDeviceProperties(&prop, p->device));
+
+    // ---- lengths (Sec. 2.1: a_w, M_w divide L; zero padding) ----
+    int64_t q = 1, need = 0;
+    for (int w = 0; w < W; ++w) {
+      q = q / gcd64(q, dicts[w].a) * dicts[w].a;
+      q = q / gcd64(q, dicts[w].M) * dicts[w].M;
+      for (int v = 0; v < W; ++v) need = std::max<int64_t>(need, dicts[w].gl + dicts[v].gl);
+    }
+    p->hs.resize(batch);
+    int64_t xoff = 0, cbase = 0;
+    for (int s = 0; s < batch; ++s) {
+      SigDev& S = p->hs[s];
+      memset(&S, 0, sizeof(S));
+      S.L = L[s];
+      S.Lp = (L[s] + q - 1) / q * q;
+      if (S.Lp < need) {
+        rc = MP_E_LEN;
+        goto fail;
+      }
+      if (S.Lp >= (int64_t)1 << 30) {
+        rc = MP_E_LIMIT;
+        goto fail;
+      }
+      S.x_off = xoff;
+      xoff += S.L;
+      int64_t off = 0;
+      for (int w = 0; w < W; ++w) {
+        S.N[w] = (int32_t)(S.Lp / dicts[w].a);
+        S.off[w] = off;
+        const int64_t sz = (int64_t)S.N[w] * (dicts[w].M / 2 + 1);
+        off += (sz + BLK - 1) / BLK * BLK;
+      }
+      S.off[W] = off;
+      for (int w = W + 1; w <= MAXW; ++w) S.off[w] = off;
+      if (off >= ((int64_t)1 << 31) - BLK) {
+        rc = MP_E_LIMIT;
+        goto fail;
+      }
+      S.n_coef_padded = off;
+      S.coef_base = cbase;
+      cbase += off;
+      S.n_leaves = (int32_t)(off / BLK);
+      p->max_Lp = std::max(p->max_Lp, S.Lp);
+    }
+    p->total_coef = cbase;
+    p->total_leaves = cbase / BLK;
+    // group size: keep the per-workgroup group maxima within 48 KiB of LDS
+    {
+      int maxleaves = 0;
+      for (auto& S : p->hs) maxleaves = std::max(maxleaves, S.n_leaves);
+      const size_t lb = leaf_bytes(p->f64);
+      p->G = 64;
+      p->logG = 6;
+      while ((size_t)((maxleaves + p->G - 1) / p->G) * lb > 48 * 1024) {
+        p->G *= 2;
+        p->logG += 1;
+      }
+      p->n_groups_max = 0;
+      for (auto& S : p->hs) {
+        S.n_groups = (S.n_leaves + p->G - 1) / p->G;
+        p->n_groups_max = std::max(p->n_groups_max, S.n_groups);
+      }
+      p->shmem = (size_t)p->n_groups_max * lb;
+    }
+    // atom logs (default capacity L_padded / 5)
+    {
+      int64_t base = 0;
+      for (auto& S : p->hs) {
+        S.atom_base = base;
+        S.cap = std::max<int64_t>(S.Lp / 5, 1);
+        base += S.cap;
+      }
+      p->total_cap = base;
+    }
+
+    HCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+
+    // ---- windows and DFT twiddles ----
+    p->hd.resize(W);
+    {
+      std::vector<double> w64;
+      std::vector<float> w32;
+      int64_t twoff = 0, gamoff = 0;
+      for (int w = 0; w < W; ++w) {
+        std::vector<double> g;
+        make_window(dicts[w].window, dicts[w].gl, g);
+        DictDev& D = p->hd[w];
+        D.gl = dicts[w].gl;
+        D.a = dicts[w].a;
+        D.M = dicts[w].M;
+        D.MR = dicts[w].M / 2 + 1;
+        D.win_off = (int64_t)w64.size();
+        D.tw_off = twoff;
+        D.gamma_off = gamoff;
+        twoff += std::max(D.M / 2, 1);
+        gamoff += D.MR;
+        for (double v : g) {
+          w64.push_back(v);
+          w32.push_back((float)v);
+        }
+      }
+      ACHK(dalloc(&p->d_win64, w64.size()));
+      ACHK(dalloc(&p->d_win32, w32.size()));
+      HCHK(hipMemcpy(p->d_win64, w64.data(), w64.size() * sizeof(double), hipMemcpyHostToDevice));
+      HCHK(hipMemcpy(p->d_win32, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice));
+      ACHK(dalloc(&p->d_tw64, (size_t)twoff));
+      ACHK(dalloc(&p->d_tw32, (size_t)twoff));
+      for (int w = 0; w < W; ++w)
+        HCHK(launch_roots(p->hd[w].M, p->hd[w].M / 2, -1, p->d_tw64 + p->hd[w].tw_off,
+                          p->d_tw32 + p->hd[w].tw_off, st));
+      ACHK(dalloc(&p->d_gam64, (size_t)gamoff));
+      ACHK(dalloc(&p->d_gam32, (size_t)gamoff));
+    }
+
+    // ---- truncated cross-kernels, FP64 on the device (Sec. 4.1, 4.2) ----
+    p->hp.resize((size_t)W * W);
+    p->kinfo.resize((size_t)W * W);
+    p->kre.resize((size_t)W * W);
+    p->kim.resize((size_t)W * W);
+    {
+      size_t full_max = 0;
+      int Mmax_all = 0;
+      for (int w = 0; w < W; ++w)
+        for (int v = 0; v < W; ++v) {
+          const int amin = std::min(dicts[w].a, dicts[v].a), Mmax = std::max(dicts[w].M, dicts[v].M);
+          const int half = (dicts[w].gl + dicts[v].gl) / 2;
+          const int D = (half + amin - 1) / amin - 1;
+          full_max = std::max(full_max, (size_t)(2 * D + 1) * (size_t)Mmax);
+          Mmax_all = std::max(Mmax_all, Mmax);
+        }
+      ACHK(dalloc(&d_full, full_max));
+      ACHK(dalloc(&d_roots, (size_t)Mmax_all));
+      ACHK(dalloc(&d_box, 4));
+      ACHK(dalloc(&d_max, 1));
+      int64_t tab_total = 0;
+      ptab64.assign((size_t)W * W, nullptr);
+      ptab32.assign((size_t)W * W, nullptr);
+      for (int w = 0; w < W; ++w)
+        for (int v = 0; v < W; ++v) {
+          const int idx = w * W + v;
+          const int amin = std::min(dicts[w].a, dicts[v].a), Mmax = std::max(dicts[w].M, dicts[v].M);
+          const int half = (dicts[w].gl + dicts[v].gl) / 2;
+          const int D = (half + amin - 1) / amin - 1;
+          HCHK(launch_roots(Mmax, Mmax, -1, d_roots, nullptr, st));
+          HCHK(launch_gram_full(p->d_win64 + p->hd[w].win_off, dicts[w].gl, p->d_win64 + p->hd[v].win_off,
+                                dicts[v].gl, amin, D, Mmax, d_roots, d_full, st));
+          double thr = kernel_tol;
+          if (flags & MP_THR_REL) {
+            unsigned long long zero = 0, mx = 0;
+            HCHK(hipMemcpyAsync(d_max, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+            HCHK(launch_gram_absmax(d_full, (int64_t)(2 * D + 1) * Mmax, d_max, st));
+            HCHK(hipMemcpyAsync(&mx, d_max, sizeof(mx), hipMemcpyDeviceToHost, st));
+            HCHK(hipStreamSynchronize(st));
+            double m;
+            memcpy(&m, &mx, sizeof(m));
+            thr = kernel_tol * m;
+          }
+          int box[4] = {-1, Mmax, -Mmax, 0};
+          HCHK(hipMemcpyAsync(d_box, box, sizeof(box), hipMemcpyHostToDevice, st));
+          HCHK(launch_gram_box(d_full, D, Mmax, thr, d_box, st));
+          HCHK(hipMemcpyAsync(box, d_box, sizeof(box), hipMemcpyDeviceToHost, st));
+          HCHK(hipStreamSynchronize(st));
+          PairDev& P = p->hp[idx];
+          P.amin = amin;
+          P.Mmax = Mmax;
+          P.rw = Mmax / dicts[w].M;
+          P.rv = Mmax / dicts[v].M;
+          if (box[3] > 0) {
+            P.dbox = box[0];
+            P.mu_lo = box[1];
+            P.mu_hi = box[2];
+          } else {
+            P.dbox = -1;
+            P.mu_lo = 0;
+            P.mu_hi = -1;
+          }
+          P.width = P.mu_hi - P.mu_lo + 1;
+          const size_t n = P.dbox >= 0 ? (size_t)(2 * P.dbox + 1) * (size_t)P.width : 0;
+          P.tab_off = tab_total;
+          tab_total += (int64_t)n;
+          mp_kernel_info& KI = p->kinfo[idx];
+          KI.amin = amin;
+          KI.Mmax = Mmax;
+          KI.D = D;
+          KI.delta_box = P.dbox;
+          KI.mu_lo = P.mu_lo;
+          KI.mu_hi = P.mu_hi;
+          KI.n_nonzero = box[3];
+          if (n) {
+            ACHK(dalloc(&ptab64[idx], n));
+            ACHK(dalloc(&ptab32[idx], n));
+            HCHK(launch_gram_extract(d_full, D, Mmax, thr, P.dbox, P.mu_lo, P.width, ptab64[idx],
+                                     ptab32[idx], st));
+            std::vector<double2> host(n);
+            HCHK(hipMemcpyAsync(host.data(), ptab64[idx], n * sizeof(double2), hipMemcpyDeviceToHost, st));
+            HCHK(hipStreamSynchronize(st));
+            p->kre[idx].resize(n);
+            p->kim[idx].resize(n);
+            for (size_t i = 0; i < n; ++i) {
+              p->kre[idx][i] = host[i].x;
+              p->kim[idx][i] = host[i].y;
+            }
+          }
+        }
+      ACHK(dalloc(&p->d_tab64, (size_t)tab_total));
+      ACHK(dalloc(&p->d_tab32, (size_t)tab_total));
+      for (int i = 0; i < W * W; ++i) {
+        const PairDev& P = p->hp[i];
+        const size_t n = P.dbox >= 0 ? (size_t)(2 * P.dbox + 1) * (size_t)P.width : 0;
+        if (!n) continue;
+        HCHK(hipMemcpyAsync(p->d_tab64 + P.tab_off, ptab64[i], n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        HCHK(hipMemcpyAsync(p->d_tab32 + P.tab_off, ptab32[i], n * sizeof(float2), hipMemcpyDeviceToDevice, st));
+      }
+      // gamma(k) = <d, conj d> = h_{v,v}(-2k mod M_v, 0) of the truncated auto kernel (Sec. 5.2)
+      std::vector<double2> g64;
+      std::vector<float2> g32;
+      for (int v = 0; v < W; ++v) {
+        const PairDev& P = p->hp[v * W + v];
+        const int M = dicts[v].M;
+        for (int k = 0; k <= M / 2; ++k) {
+          int mu = (-2 * k) % M;
+          if (mu < 0) mu += M;
+          if (mu > M / 2) mu -= M;
+          double re = 0.0, im = 0.0;
+          if (P.dbox >= 0 && mu >= P.mu_lo && mu <= P.mu_hi) {
+            const size_t i = (size_t)P.dbox * P.width + (size_t)(mu - P.mu_lo);
+            re = p->kre[v * W + v][i];
+            im = p->kim[v * W + v][i];
+          }
+          g64.push_back(make_double2(re, im));
+          g32.push_back(make_float2((float)re, (float)im));
+        }
+      }
+      HCHK(hipMemcpy(p->d_gam64, g64.data(), g64.size() * sizeof(double2), hipMemcpyHostToDevice));
+      HCHK(hipMemcpy(p->d_gam32, g32.data(), g32.size() * sizeof(float2), hipMemcpyHostToDevice));
+    }
+
+    // ---- per-signal buffers ----
+    ACHK(dalloc(&p->d_dicts, (size_t)W));
+    HCHK(hipMemcpy(p->d_dicts, p->hd.data(), sizeof(DictDev) * W, hipMemcpyHostToDevice));
+    ACHK(dalloc(&p->d_pairs, (size_t)W * W));
+    HCHK(hipMemcpy(p->d_pairs, p->hp.data(), sizeof(PairDev) * W * W, hipMemcpyHostToDevice));
+    ACHK(dalloc(&p->d_sigs, (size_t)batch));
+    HCHK(hipMemcpy(p->d_sigs, p->hs.data(), sizeof(SigDev) * batch, hipMemcpyHostToDevice));
+    ACHK(dalloc(&p->d_state, (size_t)batch));
+    HCHK(hipMemset(p->d_state, 0, sizeof(SigState) * batch));
+    const size_t cb = p->f64 ? 16 : 8;
+    HCHK(hipMalloc(&p->d_planes, (size_t)p->total_coef * cb));
+    HCHK(hipMemset(p->d_planes, 0, (size_t)p->total_coef * cb));
+    HCHK(hipMalloc(&p->d_leaves, (size_t)std::max<int64_t>(p->total_leaves, 1) * leaf_bytes(p->f64)));
+    ACHK(dalloc(&p->d_atoms, (size_t)p->total_cap));
+    ACHK(dalloc(&p->d_acc, (size_t)p->max_Lp));
+    // longest signals first
+    p->order.resize(batch);
+    std::iota(p->order.begin(), p->order.end(), 0);
+    std::stable_sort(p->order.begin(), p->order.end(),
+                     [&](int a, int b) { return p->hs[a].Lp > p->hs[b].Lp; });
+    ACHK(dalloc(&p->d_order, (size_t)batch));
+    HCHK(hipMemcpy(p->d_order, p->order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice));
+    ACHK(dalloc(&p->d_queue, 1));
+    p->frames_total.assign(W, 0);
+    for (int w = 0; w < W; ++w) {
+      std::vector<int64_t> pre(batch);
+      int64_t acc = 0;
+      for (int s = 0; s < batch; ++s) {
+        pre[s] = acc;
+        acc += p->hs[s].N[w];
+      }
+      p->frames_total[w] = acc;
+      ACHK(dalloc(&p->d_fprefix[w], (size_t)batch));
+      HCHK(hipMemcpy(p->d_fprefix[w], pre.data(), sizeof(int64_t) * batch, hipMemcpyHostToDevice));
+    }
+    for (auto& e : p->ev) HCHK(hipEventCreate(&e));
+    p->ev_valid = true;
+
+    // launch shape of the MP loop
+    p->nt = p->f64 ? 256 : 512;
+    if (const char* e = getenv("MPG_NT")) {
+      const int v = atoi(e);
+      if (v == 256 || v == 512 || (v == 1024 && !p->f64)) p->nt = v;
+    }
+    p->grid = std::min(batch, 2 * prop.multiProcessorCount);
+    HCHK(hipStreamSynchronize(st));
+  }
+  for (auto t : ptab64) hipFree(t);
+  for (auto t : ptab32) hipFree(t);
+  hipFree(d_full);
+  hipFree(d_roots);
+  hipFree(d_box);
+  hipFree(d_max);
+  hipStreamDestroy(st);
+  *out = p;
+  return MP_OK;
+
+fail:
+  if (st) {
+    hipStreamSynchronize(st);
+    hipStreamDestroy(st);
+  }
+  for (auto t : ptab64) hipFree(t);
+  for (auto t : ptab32) hipFree(t);
+  hipFree(d_full);
+  hipFree(d_roots);
+  hipFree(d_box);
+  hipFree(d_max);
+  free_plan(p);
+  return rc;
+}
+
+int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream) {
+  if (!p || !x_dev || (dtype != MP_DTYPE_F32 && dtype != MP_DTYPE_F64)) return MP_E_ARG;
+  int rc = MP_OK;
+  const void* win = p->f64 ? (const void*)p->d_win64 : (const void*)p->d_win32;
+  HCHK(hipEventRecord(p->ev[0], stream));
+  HCHK(launch_energy(x_dev, dtype, p->d_sigs, p->batch, p->d_state, stream));
+  for (int w = 0; w < p->W; ++w) {
+    const DictDev& D = p->hd[w];
+    const void* tw = p->f64 ? (const void*)(p->d_tw64 + D.tw_off) : (const void*)(p->d_tw32 + D.tw_off);
+    HCHK(launch_dgt(p->f64, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w], p->batch,
+                    p->frames_total[w], (const char*)win + D.win_off * (p->f64 ? 8 : 4), tw, p->d_planes,
+                    stream));
+  }
+  HCHK(hipEventRecord(p->ev[1], stream));
+  HCHK(launch_leaves(p->f64, p->d_planes, p->d_leaves, p->d_sigs, p->batch, p->W, p->d_dicts,
+                     p->total_leaves, stream));
+  HCHK(hipEventRecord(p->ev[2], stream));
+  p->analyzed = true;
+  p->ran = false;
+  p->last_stream = stream;
+  return MP_OK;
+fail:
+  return rc;
+}
+
+int mp_run(mp_plan* p, int64_t max_atoms, double target_snr_db, hipStream_t stream) {
+  if (!p) return MP_E_ARG;
+  if (!p->analyzed) return MP_E_STATE;
+  int rc = ensure_cap(p, max_atoms, stream);
+  if (rc) return rc;
+  MPArgs a;
+  a.dicts = p->d_dicts;
+  a.pairs = p->d_pairs;
+  a.sigs = p->d_sigs;
+  a.state = p->d_state;
+  a.planes = p->d_planes;
+  a.leaves = p->d_leaves;
+  a.atoms = p->d_atoms;
+  a.tabs = p->f64 ? (const void*)p->d_tab64 : (const void*)p->d_tab32;
+  a.gammas = p->f64 ? (const void*)p->d_gam64 : (const void*)p->d_gam32;
+  a.order = p->d_order;
+  a.queue = p->d_queue;
+  a.W = p->W;
+  a.batch = p->batch;
+  a.G = p->G;
+  a.logG = p->logG;
+  a.K = max_atoms;
+  a.snr_db = target_snr_db;
+  a.partner_gate = (p->flags & MP_CONJ_GATE_GAMMA) ? 1u : 0u;
+  HCHK(hipEventRecord(p->ev[3], stream));
+  HCHK(launch_mp(p->f64, p->nt, a, p->grid, p->shmem, stream));
+  HCHK(hipEventRecord(p->ev[4], stream));
+  p->last_stream = stream;
+  p->last_K = max_atoms;
+  p->ran = true;
+  return MP_OK;
+fail:
+  return rc;
+}
+
+int mp_signal_info_get(const mp_plan* p, int32_t sig, mp_signal_info* out) {
+  if (!p || !out || sig < 0 || sig >= p->batch) return MP_E_ARG;
+  if (hipStreamSynchronize(p->last_stream) != hipSuccess) return MP_E_HIP;
+  SigState st;
+  if (hipMemcpy(&st, p->d_state + sig, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return MP_E_HIP;
+  const SigDev& S = p->hs[sig];
+  out->L = S.L;
+  out->L_padded = S.Lp;
+  out->x_offset = S.x_off;
+  int64_t nc = 0;
+  for (int w = 0; w < p->W; ++w) nc += (int64_t)S.N[w] * p->hd[w].MR;
+  out->n_coefs = nc;
+  out->n_atoms = p->analyzed ? st.k : 0;
+  out->stop_reason = p->analyzed ? st.stop : 0;
+  out->pad = 0;
+  out->E0 = st.E0;
+  out->E = st.E;
+  return MP_OK;
+}
+
+int mp_get_atoms(const mp_plan* p, int32_t sig, mp_atom* out_host, int64_t cap, int64_t* n_out) {
+  if (!p || sig < 0 || sig >= p->batch || cap < 0 || (cap > 0 && !out_host)) return MP_E_ARG;
+  mp_signal_info inf;
+  int rc = mp_signal_info_get(p, sig, &inf);
+  if (rc) return rc;
+  if (n_out) *n_out = inf.n_atoms;
+  const int64_t n = std::min(cap, inf.n_atoms);
+  if (n > 0 && hipMemcpy(out_host, p->d_atoms + p->hs[sig].atom_base, sizeof(AtomRec) * (size_t)n,
+                         hipMemcpyDeviceToHost) != hipSuccess)
+    return MP_E_HIP;
+  return MP_OK;
+}
+
+int mp_get_energy(const mp_plan* p, int32_t sig, double* E_host, int64_t cap, int64_t* n_out) {
+  if (!p || sig < 0 || sig >= p->batch || cap < 0 || (cap > 0 && !E_host)) return MP_E_ARG;
+  mp_signal_info inf;
+  int rc = mp_signal_info_get(p, sig, &inf);
+  if (rc) return rc;
+  if (n_out) *n_out = inf.n_atoms + 1;
+  if (cap == 0) return MP_OK;
+  E_host[0] = inf.E0;
+  const int64_t n = std::min(cap - 1, inf.n_atoms);
+  if (n > 0) {
+    std::vector<AtomRec> a((size_t)n);
+    if (hipMemcpy(a.data(), p->d_atoms + p->hs[sig].atom_base, sizeof(AtomRec) * (size_t)n,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return MP_E_HIP;
+    for (int64_t i = 0; i < n; ++i) E_host[i + 1] = a[(size_t)i].E_after;
+  }
+  return MP_OK;
+}
+
+int mp_get_coefs(const mp_plan* p, int32_t sig, int32_t w, void* c_dev, hipStream_t stream) {
+  if (!p || !c_dev || sig < 0 || sig >= p->batch || w < 0 || w >= p->W) return MP_E_ARG;
+  if (!p->analyzed) return MP_E_STATE;
+  const SigDev& S = p->hs[sig];
+  const int64_t n = (int64_t)S.N[w] * p->hd[w].MR;
+  if (launch_coefs(p->d_atoms + S.atom_base, p->d_state + sig, w, p->hd[w].MR, n, c_dev, stream) != hipSuccess)
+    return MP_E_HIP;
+  return MP_OK;
+}
+
+int mp_get_residual(const mp_plan* p, int32_t sig, int32_t w, void* dst_dev, hipStream_t stream) {
+  if (!p || !dst_dev || sig < 0 || sig >= p->batch || w < 0 || w >= p->W) return MP_E_ARG;
+  if (!p->analyzed) return MP_E_STATE;
+  const SigDev& S = p->hs[sig];
+  const size_t cb = p->f64 ? 16 : 8;
+  const int64_t n = (int64_t)S.N[w] * p->hd[w].MR;
+  const char* src = (const char*)p->d_planes + (size_t)(S.coef_base + S.off[w]) * cb;
+  if (hipMemcpyAsync(dst_dev, src, (size_t)n * cb, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return MP_E_HIP;
+  return MP_OK;
+}
+
+int mp_resynth(const mp_plan* p, int32_t sig, void* y_dev, int32_t dtype, hipStream_t stream) {
+  if (!p || !y_dev || sig < 0 || sig >= p->batch || (dtype != MP_DTYPE_F32 && dtype != MP_DTYPE_F64))
+    return MP_E_ARG;
+  if (!p->analyzed) return MP_E_STATE;
+  const SigDev& S = p->hs[sig];
+  if (launch_resynth(p->d_atoms + S.atom_base, p->d_state + sig, p->d_dicts, p->d_win64, S.Lp, p->d_acc, y_dev,
+                     dtype, stream) != hipSuccess)
+    return MP_E_HIP;
+  return MP_OK;
+}
+
+int mp_kernel_info_get(const mp_plan* p, int32_t w, int32_t v, mp_kernel_info* out) {
+  if (!p || !out || w < 0 || v < 0 || w >= p->W || v >= p->W) return MP_E_ARG;
+  *out = p->kinfo[(size_t)w * p->W + v];
+  return MP_OK;
+}
+
+int mp_get_kernel(const mp_plan* p, int32_t w, int32_t v, double* re, double* im, int64_t cap) {
+  if (!p || w < 0 || v < 0 || w >= p->W || v >= p->W || cap < 0) return MP_E_ARG;
+  const size_t i = (size_t)w * p->W + v;
+  const int64_t n = (int64_t)p->kre[i].size();
+  if (cap < n || (n > 0 && (!re || !im))) return MP_E_ARG;
+  if (n) {
+    memcpy(re, p->kre[i].data(), sizeof(double) * (size_t)n);
+    memcpy(im, p->kim[i].data(), sizeof(double) * (size_t)n);
+  }
+  return MP_OK;
+}
+
+int mp_get_stats(const mp_plan* p, mp_stats* out) {
+  if (!p || !out) return MP_E_ARG;
+  memset(out, 0, sizeof(*out));
+  if (!p->analyzed) return MP_OK;
+  if (hipStreamSynchronize(p->last_stream) != hipSuccess) return MP_E_HIP;
+  std::vector<SigState> st((size_t)p->batch);
+  if (hipMemcpy(st.data(), p->d_state, sizeof(SigState) * (size_t)p->batch, hipMemcpyDeviceToHost) != hipSuccess)
+    return MP_E_HIP;
+  for (auto& s : st) {
+    out->atoms += s.k;
+    out->updated += s.updated;
+    out->blocks += s.blocks;
+    out->l1_groups += s.groups;
+  }
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, p->ev[0], p->ev[2]) == hipSuccess) out->analyze_ms = ms;
+  if (hipEventElapsedTime(&ms, p->ev[0], p->ev[1]) == hipSuccess) out->dgt_ms = ms;
+  if (p->ran && hipEventElapsedTime(&ms, p->ev[3], p->ev[4]) == hipSuccess) out->loop_ms = ms;
+  return MP_OK;
+}
+
+int mp_plan_destroy(mp_plan* p) {
+  if (!p) return MP_E_ARG;
+  if (p->last_stream) hipStreamSynchronize(p->last_stream);
+  hipDeviceSynchronize();
+  free_plan(p);
+  return MP_OK;
+}
+
+}  // extern "C"

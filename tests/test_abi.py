@@ -1,0 +1,63 @@
+"""Host-only checks of the C-ABI library: it loads, exports every function that
+include/mpg.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mpg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_boundary():
+    names = _declared()
+    for n in ["mp_plan_create", "mp_analyze", "mp_run", "mp_get_atoms", "mp_get_coefs",
+              "mp_get_energy", "mp_resynth", "mp_plan_destroy", "mp_strerror"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2202_12380_amd import mpg
+    L = mpg.lib()
+    for n in _declared():
+        assert hasattr(L, n), n
+    assert set(mpg.EXPORTS) == set(_declared())
+
+
+def test_strerror_and_argument_errors_without_gpu():
+    from paper_2202_12380_amd import mpg
+    L = mpg.lib()
+    assert L.mp_strerror(0) == b"ok"
+    assert b"incompatible" in L.mp_strerror(mpg.MP_E_GRID)
+    cases = [
+        ([(0, 64, 16, 64), (0, 64, 24, 96)], [1024], 1e-4, 0, mpg.MP_E_GRID),   # M not a power of 2
+        ([(0, 64, 16, 64), (0, 128, 48, 128)], [1024], 1e-4, 0, mpg.MP_E_GRID), # a not nested
+        ([(0, 128, 16, 64)], [1024], 1e-4, 0, mpg.MP_E_GRID),                   # gl > M
+        ([(0, 64, 48, 64)], [1024], 1e-4, 0, mpg.MP_E_GRID),                    # M/a not integer
+        ([(0, 64, 16, 64)], [64], 1e-4, 0, mpg.MP_E_LEN),                       # too short
+        ([(0, 64, 16, 64)], [0], 1e-4, 0, mpg.MP_E_ARG),
+        ([(0, 64, 16, 64)], [1024], 1.5, 0, mpg.MP_E_ARG),                      # eps >= 1
+        ([(5, 64, 16, 64)], [1024], 1e-4, 0, mpg.MP_E_ARG),                     # window
+        ([(0, 64, 16, 64)], [1024], 1e-4, 0x100, mpg.MP_E_ARG),                 # flags
+    ]
+    for dicts, lens, eps, flags, code in cases:
+        with pytest.raises(mpg.MPError) as e:
+            mpg.mp_plan_create(dicts, lens, eps, flags)
+        assert e.value.code == code, (dicts, lens, e.value.code)
+    # null handles
+    assert L.mp_plan_destroy(None) == mpg.MP_E_ARG
+    assert L.mp_run(None, 0, 0.0, None) == mpg.MP_E_ARG
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2202_12380_amd import mpg
+    monkeypatch.setattr(mpg, "_lib", None)
+    monkeypatch.setattr(mpg, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        mpg.lib()
