@@ -26,11 +26,10 @@ hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch
                          hipStream_t st);
 hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
-                      const void* win, const void* tw, void* planes, hipStream_t st);
-hipError_t launch_leaves(bool f64, const void* planes, void* leaves, const SigDev* sigs, int batch, int W,
-                         const DictDev* dicts, int64_t total_blocks, hipStream_t st);
+                      const void* win, const void* tw, void* planes, void* leaves, hipStream_t st);
 size_t leaf_bytes(bool f64);
-hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, size_t shmem, hipStream_t st);
+size_t mp_shmem_bytes(bool f64, int nt, int n_groups_max, bool preload);
+hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st);
 hipError_t launch_resynth(const AtomRec* atoms, const SigState* st_, const DictDev* dicts,
                           const double* win64, int64_t Lp, double* acc, void* y, int dtype,
                           hipStream_t st);
@@ -75,6 +74,8 @@ struct mp_plan {
   float2* d_tab32 = nullptr;
   double2* d_gam64 = nullptr;
   float2* d_gam32 = nullptr;
+  double2* d_root64 = nullptr;
+  float2* d_root32 = nullptr;
   void* d_planes = nullptr;
   void* d_leaves = nullptr;
   AtomRec* d_atoms = nullptr;
@@ -98,6 +99,14 @@ int64_t gcd64(int64_t a, int64_t b) {
     b = t;
   }
   return a;
+}
+
+// Magic pair for q / d with 0 <= q < 2^31: q / d == (umulhi(q, m) + q) >> s.
+void magic_u32(uint32_t d, uint32_t* m, int32_t* s) {
+  int sh = 0;
+  while ((1ull << sh) < d) ++sh;
+  *m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << sh) - d)) / d + 1);
+  *s = sh;
 }
 
 template <typename T>
@@ -138,6 +147,8 @@ void free_plan(mp_plan* p) {
   hipFree(p->d_tab32);
   hipFree(p->d_gam64);
   hipFree(p->d_gam32);
+  hipFree(p->d_root64);
+  hipFree(p->d_root32);
   hipFree(p->d_planes);
   hipFree(p->d_leaves);
   hipFree(p->d_atoms);
@@ -303,62 +314,62 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       q = q / gcd64(q, dicts[w].M) * dicts[w].M;
       for (int v = 0; v < W; ++v) need = std::max<int64_t>(need, dicts[w].gl + dicts[v].gl);
     }
+    // tree group size: keep the per-workgroup group nodes within 32 KiB of LDS
+    {
+      const size_t node = p->f64 ? 32 : 16;
+      int64_t maxl = 0;
+      for (int s = 0; s < batch; ++s) {
+        const int64_t Lp = (L[s] + q - 1) / q * q;
+        int64_t c = 0;
+        for (int w = 0; w < W; ++w) c += (Lp / dicts[w].a) * ((dicts[w].M / 2 + 1 + ROW - 1) / ROW);
+        maxl = std::max(maxl, c);
+      }
+      p->G = GLEAVES;
+      p->logG = 8;
+      while ((size_t)((maxl + p->G - 1) / p->G + W) * node > 32 * 1024) {
+        p->G *= 2;
+        p->logG += 1;
+      }
+    }
     p->hs.resize(batch);
-    int64_t xoff = 0, cbase = 0;
+    int64_t xoff = 0, cbase = 0, lbase_all = 0;
     for (int s = 0; s < batch; ++s) {
       SigDev& S = p->hs[s];
       memset(&S, 0, sizeof(S));
       S.L = L[s];
       S.Lp = (L[s] + q - 1) / q * q;
-      if (S.Lp < need) {
-        rc = MP_E_LEN;
-        goto fail;
-      }
-      if (S.Lp >= (int64_t)1 << 30) {
-        rc = MP_E_LIMIT;
-        goto fail;
-      }
       S.x_off = xoff;
       xoff += S.L;
-      int64_t off = 0;
+      int64_t off = 0, lb = 0;
       for (int w = 0; w < W; ++w) {
+        const int MR = dicts[w].M / 2 + 1, lpf = (MR + ROW - 1) / ROW;
         S.N[w] = (int32_t)(S.Lp / dicts[w].a);
         S.off[w] = off;
-        const int64_t sz = (int64_t)S.N[w] * (dicts[w].M / 2 + 1);
-        off += (sz + BLK - 1) / BLK * BLK;
+        off += (int64_t)S.N[w] * MR;
+        S.lbase[w] = lb;
+        lb += ((int64_t)S.N[w] * lpf + p->G - 1) / p->G * p->G;
       }
-      S.off[W] = off;
-      for (int w = W + 1; w <= MAXW; ++w) S.off[w] = off;
-      if (off >= ((int64_t)1 << 31) - BLK) {
+      for (int w = W; w <= MAXW; ++w) {
+        S.off[w] = off;
+        S.lbase[w] = lb;
+      }
+      if (off >= ((int64_t)1 << 31) - ROW || lb >= ((int64_t)1 << 31)) {
         rc = MP_E_LIMIT;
         goto fail;
       }
-      S.n_coef_padded = off;
+      S.n_coef_padded = (off + ROW - 1) / ROW * ROW;
       S.coef_base = cbase;
-      cbase += off;
-      S.n_leaves = (int32_t)(off / BLK);
+      cbase += S.n_coef_padded;
+      S.leaf_base = lbase_all;
+      lbase_all += lb;
+      S.n_leaves = (int32_t)lb;
+      S.n_groups = (int32_t)(lb / p->G);
       p->max_Lp = std::max(p->max_Lp, S.Lp);
     }
     p->total_coef = cbase;
-    p->total_leaves = cbase / BLK;
-    // group size: keep the per-workgroup group maxima within 48 KiB of LDS
-    {
-      int maxleaves = 0;
-      for (auto& S : p->hs) maxleaves = std::max(maxleaves, S.n_leaves);
-      const size_t lb = leaf_bytes(p->f64);
-      p->G = 64;
-      p->logG = 6;
-      while ((size_t)((maxleaves + p->G - 1) / p->G) * lb > 48 * 1024) {
-        p->G *= 2;
-        p->logG += 1;
-      }
-      p->n_groups_max = 0;
-      for (auto& S : p->hs) {
-        S.n_groups = (S.n_leaves + p->G - 1) / p->G;
-        p->n_groups_max = std::max(p->n_groups_max, S.n_groups);
-      }
-      p->shmem = (size_t)p->n_groups_max * lb;
-    }
+    p->total_leaves = lbase_all;
+    p->n_groups_max = 0;
+    for (auto& S : p->hs) p->n_groups_max = std::max(p->n_groups_max, S.n_groups);
     // atom logs (default capacity L_padded / 5)
     {
       int64_t base = 0;
@@ -377,7 +388,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     {
       std::vector<double> w64;
       std::vector<float> w32;
-      int64_t twoff = 0, gamoff = 0;
+      int64_t twoff = 0, gamoff = 0, rootoff = 0;
       for (int w = 0; w < W; ++w) {
         std::vector<double> g;
         make_window(dicts[w].window, dicts[w].gl, g);
@@ -389,8 +400,13 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
         D.win_off = (int64_t)w64.size();
         D.tw_off = twoff;
         D.gamma_off = gamoff;
+        D.root_off = rootoff;
+        magic_u32((uint32_t)D.MR, &D.mr_mul, &D.mr_sh);
+        D.lpf = (D.MR + ROW - 1) / ROW;
+        D.pad = 0;
         twoff += std::max(D.M / 2, 1);
         gamoff += D.MR;
+        rootoff += D.M;
         for (double v : g) {
           w64.push_back(v);
           w32.push_back((float)v);
@@ -407,6 +423,12 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
                           p->d_tw32 + p->hd[w].tw_off, st));
       ACHK(dalloc(&p->d_gam64, (size_t)gamoff));
       ACHK(dalloc(&p->d_gam32, (size_t)gamoff));
+      // exp(+2 pi i j / M), j < M: the phases exp(2 pi i k Delta / M_v) of Eq. (hkj)
+      ACHK(dalloc(&p->d_root64, (size_t)rootoff));
+      ACHK(dalloc(&p->d_root32, (size_t)rootoff));
+      for (int w = 0; w < W; ++w)
+        HCHK(launch_roots(p->hd[w].M, p->hd[w].M, +1, p->d_root64 + p->hd[w].root_off,
+                          p->d_root32 + p->hd[w].root_off, st));
     }
 
     // ---- truncated cross-kernels, FP64 on the device (Sec. 4.1, 4.2) ----
@@ -462,6 +484,8 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
           P.Mmax = Mmax;
           P.rw = Mmax / dicts[w].M;
           P.rv = Mmax / dicts[v].M;
+          P.sw = dicts[w].a / amin;
+          P.sv = dicts[v].a / amin;
           if (box[3] > 0) {
             P.dbox = box[0];
             P.mu_lo = box[1];
@@ -545,6 +569,9 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     HCHK(hipMalloc(&p->d_planes, (size_t)p->total_coef * cb));
     HCHK(hipMemset(p->d_planes, 0, (size_t)p->total_coef * cb));
     HCHK(hipMalloc(&p->d_leaves, (size_t)std::max<int64_t>(p->total_leaves, 1) * leaf_bytes(p->f64)));
+    // padding leaves (systems rounded up to whole groups) are never written by
+    // the analysis and must read as empty keys
+    HCHK(hipMemset(p->d_leaves, 0, (size_t)std::max<int64_t>(p->total_leaves, 1) * leaf_bytes(p->f64)));
     ACHK(dalloc(&p->d_atoms, (size_t)p->total_cap));
     ACHK(dalloc(&p->d_acc, (size_t)p->max_Lp));
     // longest signals first
@@ -571,10 +598,15 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     p->ev_valid = true;
 
     // launch shape of the MP loop
-    p->nt = p->f64 ? 256 : 512;
+    p->nt = 512;
     if (const char* e = getenv("MPG_NT")) {
       const int v = atoi(e);
-      if (v == 256 || v == 512 || (v == 1024 && !p->f64)) p->nt = v;
+      if (v == 256 || v == 512) p->nt = v;
+    }
+    p->shmem = mp_shmem_bytes(p->f64, p->nt, p->n_groups_max, p->G == GLEAVES);
+    if (p->shmem > 160 * 1024) {
+      rc = MP_E_LIMIT;
+      goto fail;
     }
     p->grid = std::min(batch, 2 * prop.multiProcessorCount);
     HCHK(hipStreamSynchronize(st));
@@ -615,11 +647,9 @@ int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream)
     const void* tw = p->f64 ? (const void*)(p->d_tw64 + D.tw_off) : (const void*)(p->d_tw32 + D.tw_off);
     HCHK(launch_dgt(p->f64, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w], p->batch,
                     p->frames_total[w], (const char*)win + D.win_off * (p->f64 ? 8 : 4), tw, p->d_planes,
-                    stream));
+                    p->d_leaves, stream));
   }
   HCHK(hipEventRecord(p->ev[1], stream));
-  HCHK(launch_leaves(p->f64, p->d_planes, p->d_leaves, p->d_sigs, p->batch, p->W, p->d_dicts,
-                     p->total_leaves, stream));
   HCHK(hipEventRecord(p->ev[2], stream));
   p->analyzed = true;
   p->ran = false;
@@ -644,6 +674,9 @@ int mp_run(mp_plan* p, int64_t max_atoms, double target_snr_db, hipStream_t stre
   a.atoms = p->d_atoms;
   a.tabs = p->f64 ? (const void*)p->d_tab64 : (const void*)p->d_tab32;
   a.gammas = p->f64 ? (const void*)p->d_gam64 : (const void*)p->d_gam32;
+  a.roots = p->f64 ? (const void*)p->d_root64 : (const void*)p->d_root32;
+  a.n_groups_max = p->n_groups_max;
+  a.pad_ = 0;
   a.order = p->d_order;
   a.queue = p->d_queue;
   a.W = p->W;
@@ -654,7 +687,7 @@ int mp_run(mp_plan* p, int64_t max_atoms, double target_snr_db, hipStream_t stre
   a.snr_db = target_snr_db;
   a.partner_gate = (p->flags & MP_CONJ_GATE_GAMMA) ? 1u : 0u;
   HCHK(hipEventRecord(p->ev[3], stream));
-  HCHK(launch_mp(p->f64, p->nt, a, p->grid, p->shmem, stream));
+  HCHK(launch_mp(p->f64, p->nt, a, p->grid, stream));
   HCHK(hipEventRecord(p->ev[4], stream));
   p->last_stream = stream;
   p->last_K = max_atoms;

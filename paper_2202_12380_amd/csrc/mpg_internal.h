@@ -6,15 +6,21 @@
 namespace mpg {
 
 constexpr int MAXW = 8;        // Gabor systems per plan
-constexpr int BLK = 64;        // coefficients per max-tree leaf (one wavefront)
-constexpr int MAXB = 256;      // signals per plan (queue/order arrays are sized at plan time)
+constexpr int ROW = 16;        // coefficients per max-tree leaf (one DPP row)
+constexpr int LOG_ROW = 4;
+constexpr int GLEAVES = 256;   // leaves per group when the group preload path is used
 
 // One Gabor system.
 struct DictDev {
   int32_t gl, a, M, MR;        // MR = M/2 + 1 reduced bins
   int64_t win_off;             // offset of its window in the window arrays
-  int64_t tw_off;              // offset of its twiddle table (M/2 entries)
+  int64_t tw_off;              // offset of its DFT twiddles exp(-2 pi i j / M), j < M/2
   int64_t gamma_off;           // offset of gamma(k), k = 0..M/2
+  int64_t root_off;            // offset of exp(+2 pi i j / M), j < M (update phases)
+  uint32_t mr_mul;             // q / MR == (umulhi(q, mr_mul) + q) >> mr_sh, q < 2^31
+  int32_t mr_sh;
+  int32_t lpf;                 // max-tree leaves per frame, ceil(MR / ROW)
+  int32_t pad;
 };
 
 // Kernel of the ordered pair (target w, source v) on the common grid
@@ -23,20 +29,25 @@ struct DictDev {
 struct PairDev {
   int32_t amin, Mmax, rw, rv;  // r = M_max / M
   int32_t dbox, mu_lo, mu_hi, width;
+  int32_t sw, sv;              // a_w / a_min, a_v / a_min
   int64_t tab_off;             // entry offset of the box table
 };
 
-// One signal of the batch.  Planes of system w start at coef_base + off[w]
-// (complex entries); each plane is padded to a multiple of BLK entries so
-// that no leaf straddles two systems.
+// One signal of the batch.  Plane of system w: coef_base + off[w], N_w x MR_w
+// complex entries, bin m fastest; off[w] is also the global coefficient index
+// of (w, m = 0, n = 0).  Max-tree leaves cover 16 bins of one frame: leaf
+// (w, n, i) is leaf_base + lbase[w] + n * lpf_w + i; each system's leaves are
+// padded to whole groups of G leaves.
 struct SigDev {
   int64_t L, Lp, x_off;
-  int64_t coef_base;           // first coefficient of the signal (multiple of BLK)
-  int64_t n_coef_padded;       // sum of padded plane sizes
+  int64_t coef_base;           // first coefficient of the signal
+  int64_t n_coef_padded;       // sum_w N_w MR_w, rounded up to a multiple of ROW
   int64_t atom_base, cap;      // atom log slice
-  int32_t n_leaves, n_groups;  // leaves = n_coef_padded / BLK, groups of G leaves
+  int64_t leaf_base;           // first leaf of the signal
+  int32_t n_leaves, n_groups;  // leaves (padded) and groups of G leaves
   int32_t N[MAXW];             // frames per system
-  int64_t off[MAXW + 1];       // plane offsets within the signal (padded), off[W] = total
+  int64_t off[MAXW + 1];       // plane offsets within the signal, off[W] = total
+  int64_t lbase[MAXW + 1];     // leaf offsets within the signal, lbase[W] = n_leaves
 };
 
 // Mutable per-signal state (device).
@@ -65,9 +76,11 @@ struct MPArgs {
   AtomRec* atoms;
   const void* tabs;
   const void* gammas;
+  const void* roots;
   const int32_t* order;
   int32_t* queue;
   int32_t W, batch, G, logG;
+  int32_t n_groups_max, pad_;
   int64_t K;
   double snr_db;
   uint32_t partner_gate;

@@ -24,6 +24,8 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
   return a >= 0 ? a / b : -((-a + b - 1) / b);
 }
 __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
+__device__ __forceinline__ int floor_div32(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+__device__ __forceinline__ int ceil_div32(int a, int b) { return -floor_div32(-a, b); }
 __device__ __forceinline__ int32_t mod_pos(int32_t v, int32_t n) {
   int32_t r = v % n;
   return r < 0 ? r + n : r;
@@ -116,33 +118,6 @@ __device__ __forceinline__ Leaf<double> make_leaf(Key96 k, double re, double im)
   return l;
 }
 
-// Wave-wide maximum of (key, value): every lane returns the winner.
-template <typename R>
-__device__ __forceinline__ Leaf<R> wave_max_leaf(const Leaf<R>& mine) {
-  using KO = KeyOps<R>;
-  typename KO::Key k = leaf_key(mine);
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    typename KO::Key o = KO::shfl_xor(k, off);
-    if (KO::gt(o, k)) k = o;
-  }
-  const uint64_t own = __ballot(KO::eq(k, leaf_key(mine)));
-  const int src = __ffsll((unsigned long long)own) - 1;
-  const R re = __shfl(mine.re, src);
-  const R im = __shfl(mine.im, src);
-  return make_leaf(k, re, im);
-}
-
-// Inclusive prefix sum over the wave.
-__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    int o = __shfl_up(v, off);
-    if (lane >= off) v += o;
-  }
-  return v;
-}
-
 template <typename R>
 __device__ __forceinline__ void sincospi_(R x, R* s, R* c);
 template <>
@@ -152,6 +127,147 @@ __device__ __forceinline__ void sincospi_<float>(float x, float* s, float* c) {
 template <>
 __device__ __forceinline__ void sincospi_<double>(double x, double* s, double* c) {
   sincospi(x, s, c);
+}
+
+// --------------------------------------------------------------------------
+// Cross-lane primitives on DPP (no LDS round trips).  Every call site runs
+// with all 64 lanes active.
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t lo = dpp32<CTRL>((uint32_t)v), hi = dpp32<CTRL>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t rdlane32(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
+  return ((uint64_t)rdlane32((uint32_t)(v >> 32), l) << 32) | rdlane32((uint32_t)v, l);
+}
+__device__ __forceinline__ int uni_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni_l(int64_t v) {
+  return (int64_t)(((uint64_t)(uint32_t)uni_i((int)(v >> 32)) << 32) | (uint32_t)uni_i((int)v));
+}
+
+// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror:4, row_ror:8.
+// Applied in sequence with a max they leave every lane holding its row maximum.
+template <typename R>
+struct KeyDpp;
+
+template <>
+struct KeyDpp<float> {
+  using Key = uint64_t;
+  static __device__ __forceinline__ Key kmax(Key a, Key b) { return a > b ? a : b; }
+  static __device__ __forceinline__ Key row_max(Key k) {
+    k = kmax(k, dpp64<0xB1>(k));
+    k = kmax(k, dpp64<0x4E>(k));
+    k = kmax(k, dpp64<0x124>(k));
+    k = kmax(k, dpp64<0x128>(k));
+    return k;
+  }
+  static __device__ __forceinline__ Key lane(Key k, int l) { return rdlane64(k, l); }
+  static __device__ __forceinline__ Key sentinel() { return ~0ull; }
+  static __device__ __forceinline__ bool is_sentinel(Key k) { return k == ~0ull; }
+};
+
+template <>
+struct KeyDpp<double> {
+  using Key = Key96;
+  static __device__ __forceinline__ Key kmax(Key a, Key b) {
+    return (a.v > b.v || (a.v == b.v && a.n > b.n)) ? a : b;
+  }
+  template <int C>
+  static __device__ __forceinline__ Key mv(Key k) {
+    return Key96{dpp64<C>(k.v), dpp32<C>(k.n)};
+  }
+  static __device__ __forceinline__ Key row_max(Key k) {
+    k = kmax(k, mv<0xB1>(k));
+    k = kmax(k, mv<0x4E>(k));
+    k = kmax(k, mv<0x124>(k));
+    k = kmax(k, mv<0x128>(k));
+    return k;
+  }
+  static __device__ __forceinline__ Key lane(Key k, int l) { return Key96{rdlane64(k.v, l), rdlane32(k.n, l)}; }
+  static __device__ __forceinline__ Key sentinel() { return Key96{~0ull, ~0u}; }
+  static __device__ __forceinline__ bool is_sentinel(Key k) { return k.v == ~0ull; }
+};
+
+// Wave maximum, returned uniformly (scalar) to every lane.
+template <typename R>
+__device__ __forceinline__ typename KeyDpp<R>::Key wave_max_key(typename KeyDpp<R>::Key k) {
+  using KD = KeyDpp<R>;
+  k = KD::row_max(k);
+  return KD::kmax(KD::kmax(KD::lane(k, 0), KD::lane(k, 16)), KD::kmax(KD::lane(k, 32), KD::lane(k, 48)));
+}
+
+__device__ __forceinline__ bool key_eq(uint64_t a, uint64_t b) { return a == b; }
+__device__ __forceinline__ bool key_eq(Key96 a, Key96 b) { return a.v == b.v && a.n == b.n; }
+
+// q / d for 0 <= q < 2^31 with the divisor's magic pair (m, s).
+__device__ __forceinline__ int magic_div(int q, uint32_t m, int s) {
+  return (int)((__umulhi((uint32_t)q, m) + (uint32_t)q) >> s);
+}
+
+// Row (16-lane) maximum of non-negative |rho|^2 bit patterns; every lane of
+// a row receives the row's maximum.  FP32 values use 32-bit DPP max steps.
+__device__ __forceinline__ uint64_t val_bits(float v) { return (uint64_t)__float_as_uint(v); }
+__device__ __forceinline__ uint64_t val_bits(double v) { return (uint64_t)__double_as_longlong(v); }
+template <int CTRL>
+__device__ __forceinline__ uint32_t max_dpp32(uint32_t v) {
+  const uint32_t o = dpp32<CTRL>(v);
+  return v > o ? v : o;
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t max_dpp64(uint64_t v) {
+  const uint64_t o = dpp64<CTRL>(v);
+  return v > o ? v : o;
+}
+template <typename R>
+__device__ __forceinline__ uint64_t row_max_bits(uint64_t b);
+template <>
+__device__ __forceinline__ uint64_t row_max_bits<float>(uint64_t b) {
+  uint32_t v = (uint32_t)b;
+  v = max_dpp32<0xB1>(v);
+  v = max_dpp32<0x4E>(v);
+  v = max_dpp32<0x124>(v);
+  v = max_dpp32<0x128>(v);
+  return v;
+}
+template <>
+__device__ __forceinline__ uint64_t row_max_bits<double>(uint64_t b) {
+  b = max_dpp64<0xB1>(b);
+  b = max_dpp64<0x4E>(b);
+  b = max_dpp64<0x124>(b);
+  b = max_dpp64<0x128>(b);
+  return b;
+}
+// Wave maximum of keys, returned uniformly.  FP32 keys: maximum of the value
+// word, then of the inverted index among lanes holding that value.
+template <typename R>
+__device__ __forceinline__ typename KeyOps<R>::Key wave_max_key2(typename KeyOps<R>::Key k);
+template <>
+__device__ __forceinline__ uint64_t wave_max_key2<float>(uint64_t k) {
+  uint32_t hi = (uint32_t)(k >> 32);
+  uint32_t h = max_dpp32<0xB1>(hi);
+  h = max_dpp32<0x4E>(h);
+  h = max_dpp32<0x124>(h);
+  h = max_dpp32<0x128>(h);
+  uint32_t hm = max(max(rdlane32(h, 0), rdlane32(h, 16)), max(rdlane32(h, 32), rdlane32(h, 48)));
+  uint32_t lo = hi == hm ? (uint32_t)k : 0u;
+  uint32_t l = max_dpp32<0xB1>(lo);
+  l = max_dpp32<0x4E>(l);
+  l = max_dpp32<0x124>(l);
+  l = max_dpp32<0x128>(l);
+  const uint32_t lm = max(max(rdlane32(l, 0), rdlane32(l, 16)), max(rdlane32(l, 32), rdlane32(l, 48)));
+  return ((uint64_t)hm << 32) | lm;
+}
+template <>
+__device__ __forceinline__ Key96 wave_max_key2<double>(Key96 k) {
+  return wave_max_key<double>(k);
 }
 
 // --------------------------------------------------------------------------
@@ -291,7 +407,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
                                              int w, int gl, int a, int M, int logM, int MR,
                                              const int64_t* __restrict__ frame_prefix, int batch,
                                              const R* __restrict__ win, const Cx<R>* __restrict__ tw,
-                                             Cx<R>* __restrict__ planes) {
+                                             Cx<R>* __restrict__ planes, Leaf<R>* __restrict__ leaves) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem_raw);
   const int64_t f = blockIdx.x;
@@ -339,107 +455,211 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
   }
   Cx<R>* out = planes + S.coef_base + S.off[w] + n * MR;
   for (int m = threadIdx.x; m < MR; m += blockDim.x) out[m] = buf[m];
-}
-
-// --------------------------------------------------------------------------
-// Max-tree leaves (Sec. 5.1): one wave per block of BLK coefficients.
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_leaves(const Cx<R>* __restrict__ planes, Leaf<R>* __restrict__ leaves,
-                                                const SigDev* __restrict__ sigs, int batch, int W,
-                                                const DictDev* __restrict__ dicts, int64_t total_blocks) {
-  using KO = KeyOps<R>;
+  // max-tree leaves of this frame (Sec. 5.1): leaf i = maximum of |rho|^2 over
+  // bins 16 i .. 16 i + 15 (ties to the lowest bin), one DPP row per leaf
+  const int lpf = (MR + ROW - 1) >> LOG_ROW;
+  Leaf<R>* lf = leaves + S.leaf_base + S.lbase[w] + n * lpf;
+  const uint32_t p0 = (uint32_t)(S.off[w] + n * MR);
   const int lane = threadIdx.x & 63;
-  const int64_t b = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
-  if (b >= total_blocks) return;
-  const int64_t e = b * BLK;
-  int lo = 0, hi = batch - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (sigs[mid].coef_base <= e) lo = mid;
-    else hi = mid - 1;
+  for (int m0 = 0; m0 < lpf * ROW; m0 += blockDim.x) {
+    const int m = m0 + threadIdx.x;
+    const bool valid = m < MR;
+    Cx<R> v = {(R)0, (R)0};
+    if (valid) v = buf[m];
+    const R val = v.re * v.re + v.im * v.im;
+    const uint64_t bits = valid ? val_bits(val) : 0ull;
+    const uint64_t rm = row_max_bits<R>(bits);
+    const uint64_t bal = __ballot(valid && bits == rm);
+    const uint32_t rowbits = (uint32_t)(bal >> (lane & ~(ROW - 1))) & 0xFFFFu;
+    if (rowbits && lane == (lane & ~(ROW - 1)) + __ffs(rowbits) - 1)
+      lf[m >> LOG_ROW] = make_leaf(KeyOps<R>::make(val, p0 + (uint32_t)m), v.re, v.im);
   }
-  const SigDev& S = sigs[lo];
-  const int64_t le = e - S.coef_base + lane;  // signal-local index
-  int w = 0;
-  for (int u = 1; u < W; ++u)
-    if (le >= S.off[u]) w = u;
-  const int64_t q = le - S.off[w];
-  const bool valid = le < S.n_coef_padded && q < (int64_t)S.N[w] * dicts[w].MR;
-  Cx<R> v = {(R)0, (R)0};
-  typename KO::Key k = KO::empty();
-  if (valid) {
-    v = planes[e + lane];
-    k = KO::make(v.re * v.re + v.im * v.im, (uint32_t)le);
-  }
-  const Leaf<R> best = wave_max_leaf<R>(make_leaf(k, v.re, v.im));
-  if (lane == 0) leaves[b] = best;
 }
 
 // --------------------------------------------------------------------------
 // The MP loop (Alg. 1 with Eq. approxResDef, the real-atom pairs of Sec. 5
-// and the update of Alg. 3).  One persistent workgroup per signal, signals
-// taken from a queue (longest first).  Per selection:
-//   1. every wave reduces the group maxima kept in LDS -> the global maximum
-//      (key, rho(p)) without touching global memory;
-//   2. decode p -> (v, k, j); load gamma = <d, conj d>; per target system w
-//      the kernel box covers frames n with |n a_w - j a_v| <= dbox a_min and
-//      bins m whose mu = m r_w -/+ k r_v falls in the box;
-//   3. the covered 64-entry blocks are split over the waves; all their loads
-//      (rho, h for the atom, h for its conjugate partner) are issued before
-//      the coefficient adjustment (Eq. dualatprod) is computed;
-//   4. rho -= c h1 phi + conj(c) h2 conj(phi), phi = exp(2 pi i k Delta / M_v)
-//      (Eqs. GramKern, hkj); the block maximum is recomputed in the same
-//      pass and written as the new leaf;
-//   5. barrier; the touched groups are recomputed from their leaves into LDS;
+// and the residual update of Alg. 3).  One persistent workgroup per signal;
+// signals come from a queue, longest first.
+//
+// Tree: leaves (16 bins of one frame, global memory) -> groups of G leaves
+// (LDS) -> root (reduced from the group keys).
+//
+// Per selection:
+//   1. wave 0: root from the group keys; rho(p) sits beside its group key;
+//      decode p -> (v, k, j); for every target system w the kernel box covers
+//      frames n with |n a_w - j a_v| <= dbox a_min and the bin hull where
+//      mu = m r_w -/+ k r_v lies in [mu_lo, mu_hi]; the covered leaves form a
+//      (frame x 16-bin block) grid per target; the touched groups get slots;
+//   2. barrier; every wave takes rows of the grid (four per slot, one DPP row
+//      each), owners of touched groups preload the group's old leaves, and all
+//      loads (rho, h for the atom and for its conjugate partner, the phase
+//      exp(2 pi i k Delta / M_v) of Eqs. GramKern/hkj) are issued before the
+//      coefficient adjustment (Eq. dualatprod) is computed;
+//   3. rho -= c h1 phi + conj(c) h2 conj(phi); each row's maximum (DPP) becomes
+//      the new leaf, also written to an LDS scratch for the group owner;
+//   4. barrier; owners merge old and new leaves into the group maximum;
 //      barrier.
-// E_k is tracked in FP64 (Eq. projenfaster); every wave keeps an identical
-// copy so that the stop decision needs no communication.
+// E_k is tracked in FP64 (Eq. projenfaster) by every wave identically, so the
+// stop decision needs no communication.
 
+// Constants of the pair (target w, source v) for the current signal (LDS).
+struct __align__(16) PairC {
+  int32_t MR, N, off, lbase;
+  int32_t lpf, Mmax, rw, rv;
+  int32_t dbox, mulo, muhi, width;
+  int32_t sw, sv, Lpa, amin;
+  int32_t M, sw_sh, rw_sh, pad;
+  int64_t tab;
+  int32_t pad2[2];
+};
 
+// Constants of system w for the current signal (LDS).
+struct __align__(16) DictC {
+  int32_t off, MR, M, mr_sh;
+  uint32_t mr_mul;
+  int32_t lbase, lpf, pad;
+  int64_t gamma_off, root_off;
+};
 
-template <typename R, int NT, int SLOTS, int GSLOTS>
-__device__ void mp_signal(const MPArgs& A, int s, Leaf<R>* l1, int lane, int wave) {
+// Geometry of one target system for the current selection (LDS, written by wave 0).
+struct __align__(16) Tgt {
+  int32_t MR, N, off, lbase;
+  int32_t lpf, Mmax, rw, kr;
+  int32_t mulo, muhi, width, sw;
+  int32_t nlo, nF, dlo, ilo;
+  int32_t bpf, item_base, cph, dbox;
+  int32_t gA_lo, gA_n, gB_lo, slot_base;
+  int64_t tab;
+  int32_t pad[2];
+};
+
+// Per-selection values shared by all waves (written by wave 0).
+template <typename R>
+struct __align__(16) IterS {
+  Cx<R> rp;       // rho(p)
+  int64_t gamma_off, root_off;
+  int32_t v, kk, j, pair;
+  int32_t T_items, TG, stop, M;
+};
+
+template <typename R>
+struct MPShape;
+template <>
+struct MPShape<float> {
+  static constexpr int MAXTG = 16;  // groups merged through the LDS scratch
+};
+template <>
+struct MPShape<double> {
+  static constexpr int MAXTG = 8;
+};
+
+constexpr int SLOTMAX = 256;  // touched-group slots listed per selection
+
+template <typename R, int NT, int SLOTS>
+__host__ __device__ constexpr size_t mp_lds_bytes(int n_groups_max, bool preload) {
+  return (size_t)n_groups_max * (sizeof(typename KeyOps<R>::Key) + sizeof(Cx<R>)) +
+         (preload ? (size_t)MPShape<R>::MAXTG * GLEAVES * sizeof(Leaf<R>) : 0) + (size_t)MAXW * sizeof(Tgt) +
+         (size_t)MAXW * MAXW * sizeof(PairC) + (size_t)MAXW * sizeof(DictC) + (size_t)SLOTMAX * sizeof(int) +
+         sizeof(IterS<R>) + 64;
+}
+
+__device__ __forceinline__ int fdiv_p(int x, int d, int sh) { return sh >= 0 ? (x >> sh) : floor_div32(x, d); }
+__device__ __forceinline__ int cdiv_p(int x, int d, int sh) { return sh >= 0 ? -((-x) >> sh) : ceil_div32(x, d); }
+
+// Group of touched-group slot gs, from the targets' runs in the shared table.
+__device__ __forceinline__ int slot_to_group(const Tgt* tg, int W, int gs) {
+  int g = -1;
+  for (int u = 0; u < W; ++u) {
+    const int sbu = tg[u].slot_base, an = tg[u].gA_n;
+    const int end = u + 1 < W ? tg[u + 1].slot_base : (1 << 30);
+    if (gs >= sbu && gs < sbu + an) g = tg[u].gA_lo + gs - sbu;
+    else if (gs >= sbu + an && gs < end) g = tg[u].gB_lo + gs - sbu - an;
+  }
+  return g;
+}
+
+template <typename R, int NT, int SLOTS>
+__device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane, int wave) {
   using KO = KeyOps<R>;
+  using KD = KeyDpp<R>;
   using Key = typename KO::Key;
   constexpr int NW = NT / 64;
+  constexpr int MAXTG = MPShape<R>::MAXTG;
+  constexpr int RPR = NW * 4 * SLOTS;  // rows per round
   const SigDev& S = A.sigs[s];
   const int W = A.W;
   const int G = A.G, logG = A.logG;
+  const bool preload = (G == GLEAVES);
   const int n_leaves = S.n_leaves, n_groups = S.n_groups;
   Cx<R>* rho = reinterpret_cast<Cx<R>*>(A.planes) + S.coef_base;
-  Leaf<R>* leaves = reinterpret_cast<Leaf<R>*>(A.leaves) + S.coef_base / BLK;
+  Leaf<R>* leaves = reinterpret_cast<Leaf<R>*>(A.leaves) + S.leaf_base;
   const Cx<R>* tabs = reinterpret_cast<const Cx<R>*>(A.tabs);
   const Cx<R>* gams = reinterpret_cast<const Cx<R>*>(A.gammas);
-  const int32_t Lp = (int32_t)S.Lp;
+  const Cx<R>* roots = reinterpret_cast<const Cx<R>*>(A.roots);
+  const int Lp = (int)S.Lp;
+  const int rid = lane >> LOG_ROW, rl = lane & (ROW - 1);
 
-  // ---- group maxima from the leaves ----
+  // LDS carve-up (must match mp_lds_bytes)
+  Key* gkey = reinterpret_cast<Key*>(smem);
+  Cx<R>* gval = reinterpret_cast<Cx<R>*>(gkey + A.n_groups_max);
+  Leaf<R>* scratch = reinterpret_cast<Leaf<R>*>(gval + A.n_groups_max);
+  Tgt* tg = reinterpret_cast<Tgt*>(
+      reinterpret_cast<unsigned char*>(scratch) + (preload ? (size_t)MAXTG * GLEAVES * sizeof(Leaf<R>) : 0));
+  PairC* pc = reinterpret_cast<PairC*>(tg + MAXW);
+  DictC* dc = reinterpret_cast<DictC*>(pc + MAXW * MAXW);
+  int* slotg = reinterpret_cast<int*>(dc + MAXW);
+  IterS<R>* is = reinterpret_cast<IterS<R>*>(slotg + SLOTMAX);
+
+  // ---- per-signal constants, group maxima, scratch reset ----
+  for (int t = threadIdx.x; t < W * W; t += NT) {
+    const int w = t / W;
+    const PairDev P = A.pairs[t];
+    const DictDev Dw = A.dicts[w];
+    PairC c;
+    c.MR = Dw.MR; c.N = S.N[w]; c.off = (int)S.off[w]; c.lbase = (int)S.lbase[w];
+    c.lpf = Dw.lpf; c.Mmax = P.Mmax; c.rw = P.rw; c.rv = P.rv;
+    c.dbox = P.dbox; c.mulo = P.mu_lo; c.muhi = P.mu_hi; c.width = P.width;
+    c.sw = P.sw; c.sv = P.sv; c.Lpa = Lp / P.amin; c.amin = P.amin;
+    c.M = Dw.M;
+    c.sw_sh = (P.sw & (P.sw - 1)) ? -1 : (31 - __clz(P.sw));
+    c.rw_sh = (P.rw & (P.rw - 1)) ? -1 : (31 - __clz(P.rw));
+    c.pad = 0;
+    c.tab = P.tab_off;
+    c.pad2[0] = c.pad2[1] = 0;
+    pc[t] = c;
+  }
+  if (threadIdx.x < W) {
+    const int w = threadIdx.x;
+    const DictDev Dw = A.dicts[w];
+    DictC d;
+    d.off = (int)S.off[w]; d.MR = Dw.MR; d.M = Dw.M; d.mr_sh = Dw.mr_sh; d.mr_mul = Dw.mr_mul;
+    d.lbase = (int)S.lbase[w]; d.lpf = Dw.lpf; d.pad = 0;
+    d.gamma_off = Dw.gamma_off; d.root_off = Dw.root_off;
+    dc[w] = d;
+  }
   for (int g = wave; g < n_groups; g += NW) {
-    Leaf<R> best = make_leaf(KO::empty(), (R)0, (R)0);
+    Key best = KO::empty();
+    Cx<R> bv = {(R)0, (R)0};
     for (int i = lane; i < G; i += 64) {
       const int b = (g << logG) + i;
       if (b < n_leaves) {
         const Leaf<R> c = leaves[b];
-        if (KO::gt(leaf_key(c), leaf_key(best))) best = c;
+        if (KO::gt(leaf_key(c), best)) {
+          best = leaf_key(c);
+          bv = Cx<R>{c.re, c.im};
+        }
       }
     }
-    best = wave_max_leaf<R>(best);
-    if (lane == 0) l1[g] = best;
+    const Key wm = wave_max_key2<R>(best);
+    const uint64_t own = __ballot(key_eq(best, wm));
+    if (lane == __ffsll((unsigned long long)own) - 1) {
+      gkey[g] = wm;
+      gval[g] = bv;
+    }
   }
+  if (preload)
+    for (int i = threadIdx.x; i < MAXTG * GLEAVES; i += NT) scratch[i] = make_leaf(KD::sentinel(), (R)0, (R)0);
   __syncthreads();
-
-  // per-lane copy of target system `lane` (lanes >= W unused)
-  int d_a = 1, d_M = 2, d_MR = 1, d_N = 1;
-  int64_t d_off = 0, d_gamoff = 0;
-  if (lane < W) {
-    const DictDev D = A.dicts[lane];
-    d_a = D.a;
-    d_M = D.M;
-    d_MR = D.MR;
-    d_gamoff = D.gamma_off;
-    d_N = S.N[lane];
-    d_off = S.off[lane];
-  }
 
   SigState st = A.state[s];
   double E = st.E;
@@ -456,206 +676,222 @@ __device__ void mp_signal(const MPArgs& A, int s, Leaf<R>* l1, int lane, int wav
     if (E <= Etarget) { stop = 2; break; }
     if (E < 0.0) { stop = 3; break; }
 
-    // 1. global maximum from the group maxima
-    Leaf<R> best = make_leaf(KO::empty(), (R)0, (R)0);
-    for (int i = lane; i < n_groups; i += 64) {
-      const Leaf<R> c = l1[i];
-      if (KO::gt(leaf_key(c), leaf_key(best))) best = c;
-    }
-    best = wave_max_leaf<R>(best);
-    const Key bk = leaf_key(best);
-    if (!(KO::value(bk) > (R)0)) { stop = 4; break; }
-    const int p = uni((int)KO::index(bk));
-
-    // 2. decode p -> (v, kk, j)
-    int v = 0;
-    for (int u = 1; u < W; ++u)
-      if (p >= uni((int)__shfl(d_off, u))) v = u;
-    const int v_a = uni(__shfl(d_a, v)), v_M = uni(__shfl(d_M, v)), v_MR = uni(__shfl(d_MR, v));
-    const int q = p - uni((int)__shfl(d_off, v));
-    const int j = q / v_MR;
-    const int kk = q - j * v_MR;
-    const bool pair = kk != 0 && 2 * kk != v_M;
-    Cx<R> gam = {(R)0, (R)0};
-    if (pair) gam = gams[__shfl(d_gamoff, v) + kk];  // overlaps with the block loads below
-
-    // per-target geometry, lane t < W handles target t
-    int t_nlo = 0, t_nF = 0, t_mlo = 0, t_mhi = -1;
-    int t_amin = 1, t_Mmax = 2, t_rw = 1, t_rv = 1, t_dbox = -1, t_mulo = 0, t_muhi = -1, t_width = 0;
-    int64_t t_tab = 0;
-    if (lane < W) {
-      const PairDev P = A.pairs[lane * W + v];
-      t_amin = P.amin; t_Mmax = P.Mmax; t_rw = P.rw; t_rv = P.rv;
-      t_dbox = P.dbox; t_mulo = P.mu_lo; t_muhi = P.mu_hi; t_width = P.width; t_tab = P.tab_off;
-      if (P.dbox >= 0) {
-        const int64_t jav = (int64_t)j * v_a, span = (int64_t)P.dbox * P.amin;
-        const int64_t nlo = ceil_div(jav - span, d_a), nhi = floor_div(jav + span, d_a);
-        // bins whose mu = m rw -/+ k rv lies in [mu_lo, mu_hi] modulo M_max
-        const int kr = kk * P.rv;
-        const int half = d_M / 2;
-        int mlo = 1 << 30, mhi = -1;
-        for (int term = 0; term < 2; ++term) {
-          if (term == 1 && !pair) break;
-          const int base = term == 0 ? kr : -kr;  // m rw in base + [mu_lo, mu_hi]
-          const int A1 = (int)ceil_div(base + P.mu_lo, P.rw), B1 = (int)floor_div(base + P.mu_hi, P.rw);
-          if (B1 - A1 + 1 >= d_M) {
-            mlo = 0;
-            mhi = half;
-          } else {
-            for (int c = -1; c <= 1; ++c) {
-              const int lo = max(A1 + c * d_M, 0), hi = min(B1 + c * d_M, half);
-              if (lo <= hi) {
-                mlo = min(mlo, lo);
-                mhi = max(mhi, hi);
+    // ---- wave 0: root, decode, target grids, touched-group slots ----
+    if (wave == 0) {
+      Key best = KO::empty();
+      for (int i0 = 0; i0 < n_groups; i0 += 256) {
+        Key c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + lane + 64 * u;
+          c[u] = i < n_groups ? gkey[i] : KO::empty();
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (KO::gt(c[u], best)) best = c[u];
+      }
+      const Key bk = wave_max_key2<R>(best);
+      if (!(KO::value(bk) > (R)0)) {
+        if (lane == 0) is->stop = 1;
+      } else {
+        const int p = uni_i((int)KO::index(bk));
+        int v = 0;
+        for (int u = 1; u < W; ++u)
+          if (p >= dc[u].off) v = u;
+        v = uni_i(v);
+        const DictC Dv = dc[v];
+        const int q0 = p - Dv.off;
+        const int j = magic_div(q0, Dv.mr_mul, Dv.mr_sh);
+        const int kk = q0 - j * Dv.MR;
+        const bool pair = kk != 0 && 2 * kk != Dv.M;
+        const int vmask = Dv.M - 1;
+        int t_items = 0, t_groups = 0;
+        Tgt T;
+        if (lane < W) {
+          const PairC P = pc[lane * W + v];
+          T.MR = P.MR; T.N = P.N; T.off = P.off; T.lbase = P.lbase;
+          T.lpf = P.lpf; T.Mmax = P.Mmax; T.rw = P.rw; T.kr = kk * P.rv;
+          T.mulo = P.mulo; T.muhi = P.muhi; T.width = P.width; T.sw = P.sw;
+          T.dbox = P.dbox; T.tab = P.tab; T.pad[0] = T.pad[1] = 0;
+          T.cph = (kk * P.amin) & vmask;
+          T.nlo = 0; T.nF = 0; T.dlo = 0; T.ilo = 0; T.bpf = 1;
+          T.gA_lo = T.gA_n = T.gB_lo = 0;
+          if (P.dbox >= 0) {
+            const int jsv = j * P.sv;
+            const int nlo = cdiv_p(jsv - P.dbox, P.sw, P.sw_sh), nhi = fdiv_p(jsv + P.dbox, P.sw, P.sw_sh);
+            const int half = P.M >> 1;
+            int mlo = 1 << 30, mhi = -1;
+            for (int term = 0; term < (pair ? 2 : 1); ++term) {
+              const int base = term == 0 ? T.kr : -T.kr;  // m r_w in base + [mu_lo, mu_hi]
+              const int A1 = cdiv_p(base + P.mulo, P.rw, P.rw_sh), B1 = fdiv_p(base + P.muhi, P.rw, P.rw_sh);
+              if (B1 - A1 + 1 >= P.M) {
+                mlo = 0;
+                mhi = half;
+              } else {
+                for (int c = -1; c <= 1; ++c) {
+                  const int lo = max(A1 + c * P.M, 0), hi = min(B1 + c * P.M, half);
+                  if (lo <= hi) {
+                    mlo = min(mlo, lo);
+                    mhi = max(mhi, hi);
+                  }
+                }
+              }
+            }
+            if (mhi >= 0 && nhi >= nlo) {
+              int nl = nlo % P.N;
+              if (nl < 0) nl += P.N;
+              T.nlo = nl;
+              T.nF = nhi - nlo + 1;
+              T.dlo = nlo * P.sw - jsv;  // delta of the first frame, in [-dbox, dbox]
+              T.ilo = mlo >> LOG_ROW;
+              T.bpf = (mhi >> LOG_ROW) - T.ilo + 1;
+              t_items = ((T.nF * T.bpf) + 3) & ~3;
+              // touched groups: run A = frames nlo.., run B = wrapped frames 0..
+              const int ihi = mhi >> LOG_ROW;
+              const int nAe = min(T.nlo + T.nF - 1, T.N - 1);
+              T.gA_lo = (T.lbase + T.nlo * T.lpf + T.ilo) >> logG;
+              T.gA_n = ((T.lbase + nAe * T.lpf + ihi) >> logG) - T.gA_lo + 1;
+              t_groups = T.gA_n;
+              if (T.nlo + T.nF - 1 >= T.N) {
+                const int nBe = T.nlo + T.nF - 1 - T.N;
+                T.gB_lo = (T.lbase + T.ilo) >> logG;
+                const int gBhi = min((T.lbase + nBe * T.lpf + ihi) >> logG, T.gA_lo - 1);
+                t_groups += max(0, gBhi - T.gB_lo + 1);
               }
             }
           }
         }
-        if (mhi >= 0 && nhi >= nlo) {
-          t_nlo = (int)(((nlo % d_N) + d_N) % d_N);
-          t_nF = (int)(nhi - nlo + 1);
-          t_mlo = mlo;
-          t_mhi = mhi;
+        int ib = 0, sb = 0;
+        for (int u = 0; u < W; ++u) {
+          const int iu = (int)rdlane32((uint32_t)t_items, u), gu = (int)rdlane32((uint32_t)t_groups, u);
+          if (u < lane) {
+            ib += iu;
+            sb += gu;
+          }
+        }
+        if (lane < W) {
+          T.item_base = ib;
+          T.slot_base = sb;
+          tg[lane] = T;
+        }
+        const int T_items = (int)rdlane32((uint32_t)(ib + t_items), W - 1);
+        const int TG = (int)rdlane32((uint32_t)(sb + t_groups), W - 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int gs = lane; gs < min(TG, SLOTMAX); gs += 64) slotg[gs] = slot_to_group(tg, W, gs);
+        if (lane == 0) {
+          IterS<R> I;
+          I.rp = gval[(Dv.lbase + j * Dv.lpf + (kk >> LOG_ROW)) >> logG];
+          I.gamma_off = Dv.gamma_off;
+          I.root_off = Dv.root_off;
+          I.v = v;
+          I.kk = kk;
+          I.j = j;
+          I.pair = pair;
+          I.T_items = T_items;
+          I.TG = TG;
+          I.stop = 0;
+          I.M = Dv.M;
+          *is = I;
         }
       }
     }
-    // exclusive prefix of frame counts over targets
-    const int t_cum = wave_incl_scan(lane < W ? t_nF : 0, lane) - (lane < W ? t_nF : 0);
-    const int S_tot = uni(__shfl(t_cum, W - 1) + __shfl(t_nF, W - 1));
+    __syncthreads();
+    const IterS<R> I = *is;
+    if (I.stop) { stop = 4; break; }
+    const int v = uni_i(I.v), kk = uni_i(I.kk), j = uni_i(I.j), T_items = uni_i(I.T_items), TG = uni_i(I.TG);
+    const bool pair = uni_i(I.pair) != 0;
+    Cx<R> gam = {(R)0, (R)0};
+    if (pair) gam = gams[I.gamma_off + kk];  // consumed after the row loads are issued
+    const Cx<R>* vroots = roots + I.root_off;
+    const int vmask = uni_i(I.M) - 1;
 
-    // 3. resolve this wave's blocks (slots) and groups from the segment list:
-    //    segment = (target w, frame n) with bins [mlo, mhi]; blocks of
-    //    consecutive frames are de-duplicated, the wrapped run is clipped
-    //    below the first run.
-    int blk[SLOTS], bw[SLOTS], grp[GSLOTS];
+    const int my_gs = wave;
+    const bool own_pre = preload && my_gs < TG && my_gs < MAXTG;
+    const int my_g = my_gs < TG ? uni_i(my_gs < SLOTMAX ? slotg[my_gs] : slot_to_group(tg, W, my_gs)) : -1;
+    Leaf<R> old[4];
+    if (own_pre) {
 #pragma unroll
-    for (int i = 0; i < SLOTS; ++i) blk[i] = -1, bw[i] = 0;
-#pragma unroll
-    for (int i = 0; i < GSLOTS; ++i) grp[i] = -1;
-    int totB = 0, totG = 0;
-    auto resolve = [&](int roundB, int roundG) {
-      int baseB = 0, baseG = 0;
-      for (int c0 = 0; c0 < S_tot; c0 += 64) {
-        // every lane takes part in the shuffles below; lanes past the end
-        // compute a dummy segment and contribute no blocks
-        const int sg = min(c0 + lane, S_tot - 1);
-        int cnt = 0, cntg = 0, bl = 0, gl = 0, ws = 0;
-        {
-          for (int u = 1; u < W; ++u) {
-            const int cu = __shfl(t_cum, u), nu = __shfl(t_nF, u);
-            if (sg >= cu && nu > 0) ws = u;
-          }
-          // fields of target ws
-          const int s_nlo = __shfl(t_nlo, ws), s_cum = __shfl(t_cum, ws);
-          const int s_N = __shfl(d_N, ws), s_MR = __shfl(d_MR, ws);
-          const int s_mlo = __shfl(t_mlo, ws), s_mhi = __shfl(t_mhi, ws);
-          const int64_t s_off = __shfl(d_off, ws);
-          const int f = sg - s_cum;
-          int n = s_nlo + f;
-          if (n >= s_N) n -= s_N;
-          if (n >= s_N) n %= s_N;
-          const int64_t rowb = s_off + (int64_t)n * s_MR;
-          bl = (int)((rowb + s_mlo) >> 6);
-          int bh = (int)((rowb + s_mhi) >> 6);
-          gl = bl >> logG;
-          if (f > 0 && n > 0 && n != s_nlo) {
-            // predecessor frame n-1 is adjacent in memory
-            const int pbh = (int)((s_off + (int64_t)(n - 1) * s_MR + s_mhi) >> 6);
-            if (bl <= pbh) bl = pbh + 1;
-            gl = bl >> logG;
-            if (gl == (pbh >> logG)) ++gl;
-          }
-          if (f > 0 && n < s_nlo) {
-            const int fbl = (int)((s_off + (int64_t)s_nlo * s_MR + s_mlo) >> 6);
-            if (bh >= fbl) bh = fbl - 1;
-          }
-          cnt = bh >= bl ? bh - bl + 1 : 0;
-          const int gh = bh >> logG;
-          cntg = (cnt > 0 && gh >= gl) ? gh - gl + 1 : 0;
-          if (c0 + lane >= S_tot) cnt = cntg = 0;
-        }
-        const int incB = wave_incl_scan(cnt, lane);
-        const int incG = wave_incl_scan(cntg, lane);
-        const int chB = __shfl(incB, 63), chG = __shfl(incG, 63);
-#pragma unroll
-        for (int i = 0; i < SLOTS; ++i) {
-          const int it = wave + NW * (i + SLOTS * roundB) - baseB;
-          if (it >= 0 && it < chB) {
-            const uint64_t bal = __ballot(incB > it);
-            const int src = __ffsll((unsigned long long)bal) - 1;
-            blk[i] = uni(__shfl(bl, src) + it - (__shfl(incB, src) - __shfl(cnt, src)));
-            bw[i] = uni(__shfl(ws, src));
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < GSLOTS; ++i) {
-          const int it = wave + NW * (i + GSLOTS * roundG) - baseG;
-          if (it >= 0 && it < chG) {
-            const uint64_t bal = __ballot(incG > it);
-            const int src = __ffsll((unsigned long long)bal) - 1;
-            grp[i] = uni(__shfl(gl, src) + it - (__shfl(incG, src) - __shfl(cntg, src)));
-          }
-        }
-        baseB += chB;
-        baseG += chG;
-      }
-      totB = baseB;
-      totG = baseG;
-    };
-    resolve(0, 0);
+      for (int i = 0; i < 4; ++i) old[i] = leaves[(my_g << logG) + lane + 64 * i];
+    }
 
-    // 4. update the covered blocks, rescan them, write the leaves
+    // ---- rows of the target grids: loads, adjustment, update, rescan ----
     Cx<R> cc = {(R)0, (R)0};
     bool partner = false;
-    for (int roundB = 0;; ++roundB) {
-      if (roundB > 0) {
-        if (wave + NW * SLOTS * roundB >= totB) break;
+    for (int round = 0;; ++round) {
+      Cx<R> r[SLOTS], h1[SLOTS], h2[SLOTS], ph[SLOTS];
+      int ee[SLOTS], lfi[SLOTS], gsl[SLOTS];
+      bool act[SLOTS], rowok[SLOTS], vld[SLOTS], chg[SLOTS];
+      int cw = -1;
+      Tgt T;
 #pragma unroll
-        for (int i = 0; i < SLOTS; ++i) blk[i] = -1;
-        resolve(roundB, 1 << 20);
-      }
-      Cx<R> r[SLOTS], h1[SLOTS], h2[SLOTS];
-      int ph[SLOTS], le[SLOTS];
-      bool valid[SLOTS];
-#pragma unroll
-      for (int i = 0; i < SLOTS; ++i) {
-        r[i] = h1[i] = h2[i] = Cx<R>{(R)0, (R)0};
-        ph[i] = 0;
-        valid[i] = false;
-        le[i] = 0;
-        if (blk[i] < 0) continue;
-        const int w = bw[i];
-        const int w_a = uni(__shfl(d_a, w)), w_MR = uni(__shfl(d_MR, w)), w_N = uni(__shfl(d_N, w));
-        const int w_off = uni((int)__shfl(d_off, w));
-        const int amin = uni(__shfl(t_amin, w)), Mmax = uni(__shfl(t_Mmax, w));
-        const int rw = uni(__shfl(t_rw, w)), rv = uni(__shfl(t_rv, w));
-        const int dbox = uni(__shfl(t_dbox, w)), mulo = uni(__shfl(t_mulo, w)), muhi = uni(__shfl(t_muhi, w));
-        const int width = uni(__shfl(t_width, w));
-        const int64_t tab = __shfl(t_tab, w);
-        const int e = blk[i] * BLK + lane;
-        le[i] = e;
-        const int qq = e - w_off;
-        valid[i] = qq < w_N * w_MR;
-        if (!valid[i]) continue;
-        r[i] = rho[e];
-        const int n = qq / w_MR, m = qq - n * w_MR;
-        const int Delta = cmod(n * w_a - j * v_a, Lp);
-        const int span = dbox * amin;
-        if (Delta > span || Delta < -span) continue;
-        const int row = Delta / amin + dbox;
-        const int mu1 = cmod(m * rw - kk * rv, Mmax);
-        if (mu1 >= mulo && mu1 <= muhi) h1[i] = tabs[tab + (int64_t)row * width + (mu1 - mulo)];
-        if (pair) {
-          const int mu2 = cmod(m * rw + kk * rv, Mmax);
-          if (mu2 >= mulo && mu2 <= muhi) h2[i] = tabs[tab + (int64_t)row * width + (mu2 - mulo)];
+      for (int sl = 0; sl < SLOTS; ++sl) {
+        r[sl] = h1[sl] = h2[sl] = Cx<R>{(R)0, (R)0};
+        ph[sl] = Cx<R>{(R)1, (R)0};
+        ee[sl] = lfi[sl] = gsl[sl] = 0;
+        act[sl] = rowok[sl] = vld[sl] = chg[sl] = false;
+        const int base4 = ((round * SLOTS + sl) * NW + wave) * 4;
+        if (base4 >= T_items) continue;  // wave-uniform
+        act[sl] = true;
+        int w = 0;
+        for (int u = 1; u < W; ++u)
+          if (base4 >= tg[u].item_base) w = u;
+        w = uni_i(w);
+        if (w != cw) {
+          T = tg[w];
+          cw = w;
         }
-        ph[i] = (int)(((int64_t)kk * mod_pos(Delta, v_M)) % v_M);
+        // row t of target w's grid: frame f, 16-bin block i
+        const int t = base4 - T.item_base + rid;
+        const int bpf = T.bpf;
+        int f = (int)((float)t * __frcp_rn((float)bpf));
+        if (f * bpf > t) --f;
+        if ((f + 1) * bpf <= t) ++f;
+        const int i = T.ilo + t - f * bpf;
+        const bool ok = f < T.nF;
+        rowok[sl] = ok;
+        int n = T.nlo + f;
+        if (n >= T.N) n -= T.N;
+        const int li = T.lbase + n * T.lpf + i;
+        lfi[sl] = li;
+        {
+          const int g = li >> logG;
+          gsl[sl] = (g >= T.gA_lo && g < T.gA_lo + T.gA_n) ? T.slot_base + g - T.gA_lo
+                                                           : T.slot_base + T.gA_n + g - T.gB_lo;
+        }
+        const int m = (i << LOG_ROW) + rl;
+        const int e = T.off + n * T.MR + m;
+        ee[sl] = e;
+        if (!ok || m >= T.MR) continue;
+        vld[sl] = true;
+        r[sl] = rho[e];
+        const int d = T.dlo + f * T.sw;  // delta = Delta / a_min, in [-dbox, dbox]
+        const int mm = T.Mmax - 1;
+        int mu1 = (m * T.rw - T.kr) & mm;
+        if (mu1 > (T.Mmax >> 1)) mu1 -= T.Mmax;
+        const int64_t rowoff = T.tab + (int64_t)(d + T.dbox) * T.width - T.mulo;
+        bool any = false;
+        if (mu1 >= T.mulo && mu1 <= T.muhi) {
+          h1[sl] = tabs[rowoff + mu1];
+          any = true;
+        }
+        if (pair) {
+          int mu2 = (m * T.rw + T.kr) & mm;
+          if (mu2 > (T.Mmax >> 1)) mu2 -= T.Mmax;
+          if (mu2 >= T.mulo && mu2 <= T.muhi) {
+            h2[sl] = tabs[rowoff + mu2];
+            any = true;
+          }
+        }
+        if (any) ph[sl] = vroots[((d & vmask) * T.cph) & vmask];
+        chg[sl] = any;
       }
-      if (roundB == 0) {
+      if (round == 0) {
         // coefficient adjustment for the pair, Eq. (dualatprod), and energy
-        // decrease, Eq. (projenfaster); placed after the loads above so that
-        // the gamma load overlaps with them.
-        const R rr = best.re, ri = best.im;
+        // decrease, Eq. (projenfaster); after the loads so that gamma's load
+        // overlaps with them
+        const R rr = I.rp.re, ri = I.rp.im;
         double Et;
         if (pair) {
           const R gr = gam.re, gi = gam.im;
@@ -688,63 +924,83 @@ __device__ void mp_signal(const MPArgs& A, int s, Leaf<R>* l1, int lane, int wav
         ++k;
       }
 #pragma unroll
-      for (int i = 0; i < SLOTS; ++i) {
-        if (blk[i] < 0) continue;
-        if (!partner) h2[i] = Cx<R>{(R)0, (R)0};
-        const bool ch = (h1[i].re != (R)0) | (h1[i].im != (R)0) | (h2[i].re != (R)0) | (h2[i].im != (R)0);
-        if (ch) {
-          R sn, cs;
-          sincospi_<R>((R)2 * (R)ph[i] / (R)v_M, &sn, &cs);
-          // c * (h1 phi) + conj(c) * (h2 conj(phi))
-          const R ar = h1[i].re * cs - h1[i].im * sn, ai = h1[i].re * sn + h1[i].im * cs;
-          R ur = cc.re * ar - cc.im * ai, ui = cc.re * ai + cc.im * ar;
-          const R br = h2[i].re * cs + h2[i].im * sn, bi = h2[i].im * cs - h2[i].re * sn;
-          ur += cc.re * br + cc.im * bi;
-          ui += cc.re * bi - cc.im * br;
-          r[i].re -= ur;
-          r[i].im -= ui;
-          rho[le[i]] = r[i];
+      for (int sl = 0; sl < SLOTS; ++sl) {
+        if (!act[sl]) continue;  // wave-uniform
+        bool nz = false;
+        if (chg[sl]) {
+          const Cx<R> b2 = partner ? h2[sl] : Cx<R>{(R)0, (R)0};
+          nz = (h1[sl].re != (R)0) | (h1[sl].im != (R)0) | (b2.re != (R)0) | (b2.im != (R)0);
+          if (nz) {
+            const R cs = ph[sl].re, sn = ph[sl].im;
+            // c (h1 phi) + conj(c) (h2 conj(phi))
+            const R ar = h1[sl].re * cs - h1[sl].im * sn, ai = h1[sl].re * sn + h1[sl].im * cs;
+            R ur = cc.re * ar - cc.im * ai, ui = cc.re * ai + cc.im * ar;
+            const R br = b2.re * cs + b2.im * sn, bi = b2.im * cs - b2.re * sn;
+            ur += cc.re * br + cc.im * bi;
+            ui += cc.re * bi - cc.im * br;
+            r[sl].re -= ur;
+            r[sl].im -= ui;
+            rho[ee[sl]] = r[sl];
+          }
         }
-        Key key = valid[i] ? KO::make(r[i].re * r[i].re + r[i].im * r[i].im, (uint32_t)le[i]) : KO::empty();
-        const Leaf<R> bl = wave_max_leaf<R>(make_leaf(key, r[i].re, r[i].im));
-        const int nch = __popcll(__ballot(ch));
-        if (lane == 0) {
-          leaves[blk[i]] = bl;
-          c_upd += nch;
-          ++c_blk;
+        const R val = r[sl].re * r[sl].re + r[sl].im * r[sl].im;
+        const uint64_t bits = vld[sl] ? val_bits(val) : 0ull;
+        const uint64_t rm = row_max_bits<R>(bits);
+        const uint64_t bal = __ballot(vld[sl] && bits == rm);
+        const uint32_t rowbits = (uint32_t)(bal >> (rid * ROW)) & 0xFFFFu;
+        const bool leader = rowok[sl] && rowbits && lane == rid * ROW + __ffs(rowbits) - 1;
+        c_upd += __popcll(__ballot(nz));
+        c_blk += __popcll(__ballot(leader));
+        if (leader) {
+          const Leaf<R> nl = make_leaf(KO::make(val, (uint32_t)ee[sl]), r[sl].re, r[sl].im);
+          const int b = lfi[sl];
+          leaves[b] = nl;
+          if (preload && gsl[sl] < MAXTG) scratch[gsl[sl] * GLEAVES + (b & (GLEAVES - 1))] = nl;
         }
       }
-      if (wave + NW * SLOTS * (roundB + 1) >= totB) break;
+      if ((round + 1) * RPR >= T_items) break;
     }
     __syncthreads();
 
-    // 5. recompute the touched groups
-    for (int roundG = 0;; ++roundG) {
-      if (roundG > 0) {
-        if (wave + NW * GSLOTS * roundG >= totG) break;
+    // ---- group maxima of the touched groups ----
+    for (int gs = wave; gs < TG; gs += NW) {
+      const int g = gs == my_gs ? my_g : uni_i(gs < SLOTMAX ? slotg[gs] : slot_to_group(tg, W, gs));
+      Key bkey = KO::empty();
+      Cx<R> bval = {(R)0, (R)0};
+      if (preload && gs < MAXTG) {
 #pragma unroll
-        for (int i = 0; i < GSLOTS; ++i) grp[i] = -1;
-        resolve(1 << 20, roundG);
-      }
-#pragma unroll
-      for (int i = 0; i < GSLOTS; ++i) {
-        if (grp[i] < 0) continue;
-        const int g = grp[i];
-        Leaf<R> gb = make_leaf(KO::empty(), (R)0, (R)0);
-        for (int t = lane; t < G; t += 64) {
-          const int b = (g << logG) + t;
-          if (b < n_leaves) {
-            const Leaf<R> c = leaves[b];
-            if (KO::gt(leaf_key(c), leaf_key(gb))) gb = c;
+        for (int i = 0; i < 4; ++i) {
+          Leaf<R>& sc = scratch[gs * GLEAVES + lane + 64 * i];
+          Leaf<R> c = (gs == my_gs && own_pre) ? old[i] : leaves[(g << logG) + lane + 64 * i];
+          const Leaf<R> scv = sc;
+          if (!KD::is_sentinel(leaf_key(scv))) {
+            c = scv;
+            sc = make_leaf(KD::sentinel(), (R)0, (R)0);
+          }
+          if (KO::gt(leaf_key(c), bkey)) {
+            bkey = leaf_key(c);
+            bval = Cx<R>{c.re, c.im};
           }
         }
-        gb = wave_max_leaf<R>(gb);
-        if (lane == 0) {
-          l1[g] = gb;
-          ++c_grp;
+      } else {
+        for (int i = lane; i < G; i += 64) {
+          const int b = (g << logG) + i;
+          if (b < n_leaves) {
+            const Leaf<R> c = leaves[b];
+            if (KO::gt(leaf_key(c), bkey)) {
+              bkey = leaf_key(c);
+              bval = Cx<R>{c.re, c.im};
+            }
+          }
         }
       }
-      if (wave + NW * GSLOTS * (roundG + 1) >= totG) break;
+      const Key wm = wave_max_key2<R>(bkey);
+      const uint64_t own = __ballot(key_eq(bkey, wm));
+      if (lane == __ffsll((unsigned long long)own) - 1) {
+        gkey[g] = wm;
+        gval[g] = bval;
+      }
+      ++c_grp;
     }
     __syncthreads();
   }
@@ -761,10 +1017,9 @@ __device__ void mp_signal(const MPArgs& A, int s, Leaf<R>* l1, int lane, int wav
   }
 }
 
-template <typename R, int NT, int SLOTS, int GSLOTS>
+template <typename R, int NT, int SLOTS>
 __global__ void __launch_bounds__(NT) k_mp(MPArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Leaf<R>* l1 = reinterpret_cast<Leaf<R>*>(smem_raw);
   __shared__ int s_next;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (;;) {
@@ -773,7 +1028,7 @@ __global__ void __launch_bounds__(NT) k_mp(MPArgs A) {
     const int qi = s_next;
     __syncthreads();
     if (qi >= A.batch) break;
-    mp_signal<R, NT, SLOTS, GSLOTS>(A, A.order[qi], l1, lane, wave);
+    mp_signal<R, NT, SLOTS>(A, A.order[qi], smem_raw, lane, wave);
   }
 }
 
@@ -901,7 +1156,7 @@ hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch
 
 hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
-                      const void* win, const void* tw, void* planes, hipStream_t st) {
+                      const void* win, const void* tw, void* planes, void* leaves, hipStream_t st) {
   if (frames <= 0) return hipSuccess;
   int logM = 0;
   while ((1 << logM) < M) ++logM;
@@ -911,63 +1166,51 @@ hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, in
     if (dtype == 0)
       k_dgt<double, float><<<grid, 256, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                   batch, (const double*)win, (const Cx<double>*)tw,
-                                                  (Cx<double>*)planes);
+                                                  (Cx<double>*)planes, (Leaf<double>*)leaves);
     else
       k_dgt<double, double><<<grid, 256, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                    batch, (const double*)win, (const Cx<double>*)tw,
-                                                   (Cx<double>*)planes);
+                                                   (Cx<double>*)planes, (Leaf<double>*)leaves);
   } else {
     if (dtype == 0)
       k_dgt<float, float><<<grid, 256, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                  batch, (const float*)win, (const Cx<float>*)tw,
-                                                 (Cx<float>*)planes);
+                                                 (Cx<float>*)planes, (Leaf<float>*)leaves);
     else
       k_dgt<float, double><<<grid, 256, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                   batch, (const float*)win, (const Cx<float>*)tw,
-                                                  (Cx<float>*)planes);
+                                                  (Cx<float>*)planes, (Leaf<float>*)leaves);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_leaves(bool f64, const void* planes, void* leaves, const SigDev* sigs, int batch, int W,
-                         const DictDev* dicts, int64_t total_blocks, hipStream_t st) {
-  if (total_blocks <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)((total_blocks + 3) / 4);
-  if (f64)
-    k_leaves<double><<<grid, 256, 0, st>>>((const Cx<double>*)planes, (Leaf<double>*)leaves, sigs, batch, W,
-                                           dicts, total_blocks);
-  else
-    k_leaves<float><<<grid, 256, 0, st>>>((const Cx<float>*)planes, (Leaf<float>*)leaves, sigs, batch, W,
-                                          dicts, total_blocks);
   return hipGetLastError();
 }
 
 size_t leaf_bytes(bool f64) { return f64 ? sizeof(Leaf<double>) : sizeof(Leaf<float>); }
 
-hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, size_t shmem, hipStream_t st) {
+template <typename R, int NT, int SLOTS>
+static hipError_t launch_mp_t(const MPArgs& a, int grid, bool preload, hipStream_t st) {
+  const size_t sh = mp_lds_bytes<R, NT, SLOTS>(a.n_groups_max, preload);
+  if (sh > 160 * 1024) return hipErrorInvalidValue;
+  (void)hipFuncSetAttribute((const void*)k_mp<R, NT, SLOTS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  k_mp<R, NT, SLOTS><<<grid, NT, sh, st>>>(a);
+  return hipGetLastError();
+}
+
+size_t mp_shmem_bytes(bool f64, int nt, int n_groups_max, bool preload) {
+  if (f64) return nt == 256 ? mp_lds_bytes<double, 256, 4>(n_groups_max, preload) : mp_lds_bytes<double, 512, 4>(n_groups_max, preload);
+  if (nt == 256) return mp_lds_bytes<float, 256, 6>(n_groups_max, preload);
+  return mp_lds_bytes<float, 512, 6>(n_groups_max, preload);
+}
+
+hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st) {
   k_fill_i32<<<1, 64, 0, st>>>(a.queue, 1, 0);
   CHK(hipGetLastError());
+  const bool preload = a.G == GLEAVES;
   if (f64) {
-    if (nt == 256) {
-      (void)hipFuncSetAttribute((const void*)k_mp<double, 256, 4, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-      k_mp<double, 256, 4, 2><<<grid, 256, shmem, st>>>(a);
-    } else {
-      (void)hipFuncSetAttribute((const void*)k_mp<double, 512, 4, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-      k_mp<double, 512, 4, 1><<<grid, 512, shmem, st>>>(a);
-    }
-  } else {
-    if (nt == 256) {
-      (void)hipFuncSetAttribute((const void*)k_mp<float, 256, 4, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-      k_mp<float, 256, 4, 2><<<grid, 256, shmem, st>>>(a);
-    } else if (nt == 512) {
-      (void)hipFuncSetAttribute((const void*)k_mp<float, 512, 4, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-      k_mp<float, 512, 4, 1><<<grid, 512, shmem, st>>>(a);
-    } else {
-      (void)hipFuncSetAttribute((const void*)k_mp<float, 1024, 2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-      k_mp<float, 1024, 2, 1><<<grid, 1024, shmem, st>>>(a);
-    }
+    if (nt == 256) return launch_mp_t<double, 256, 4>(a, grid, preload, st);
+    return launch_mp_t<double, 512, 4>(a, grid, preload, st);
   }
-  return hipGetLastError();
+  if (nt == 256) return launch_mp_t<float, 256, 6>(a, grid, preload, st);
+  return launch_mp_t<float, 512, 6>(a, grid, preload, st);
 }
 
 hipError_t launch_resynth(const AtomRec* atoms, const SigState* st_, const DictDev* dicts, const double* win64,

@@ -30,6 +30,7 @@ import numpy as np
 BLACKMAN = 0
 HANN = 1
 FS = 44100.0
+_TAB = 16384
 
 
 def rng(config_id: int, signal_idx: int) -> np.random.Generator:
@@ -142,20 +143,27 @@ def audio_like(L: int, g: np.random.Generator, scale_events: bool = True) -> np.
         vr = g.uniform(4.0, 7.0)
         vd = g.uniform(0.005, 0.02)
         vph = g.uniform(0, 2 * np.pi)
-        i0 = int(on * FS)
-        n = min(int(dur * FS), L - i0)
+        i0s = int(on * FS)
+        n = min(int(dur * FS), L - i0s)
         if n <= 0:
             continue
         t = np.arange(n) / FS
         # instantaneous frequency f0 (1 + vd sin(2 pi vr t + vph)), integrated
         phase_base = 2 * np.pi * f0 * (t - vd / (2 * np.pi * vr) * (np.cos(2 * np.pi * vr * t + vph) - np.cos(vph)))
         env = _fade(n, int(0.02 * FS))
-        sig = np.zeros(n)
-        h = 1
-        while h * f0 < 16000.0:
-            sig += np.sin(h * phase_base + g.uniform(0, 2 * np.pi)) / h
-            h += 1
-        x[i0:i0 + n] += amp * env * sig
+        # one period of sum_h sin(h phi + theta_h) / h (harmonics below 16 kHz),
+        # tabulated by an inverse FFT and read by linear interpolation
+        H = max(1, int(np.ceil(16000.0 / f0)) - 1)
+        theta = g.uniform(0, 2 * np.pi, size=H)
+        spec = np.zeros(_TAB // 2 + 1, np.complex128)
+        h = np.arange(1, H + 1)
+        spec[h] = (_TAB / 2) / h * np.exp(1j * (theta - np.pi / 2))
+        table = np.fft.irfft(spec, n=_TAB)
+        pos = np.mod(phase_base, 2 * np.pi) * (_TAB / (2 * np.pi))
+        i0 = np.floor(pos).astype(np.int64) % _TAB
+        fr = pos - np.floor(pos)
+        sig = table[i0] * (1 - fr) + table[(i0 + 1) % _TAB] * fr
+        x[i0s:i0s + n] += amp * env * sig
     # linear chirps
     for _ in range(n_chirps):
         fa, fb = g.uniform(100.0, 12000.0, size=2)
@@ -180,14 +188,15 @@ def audio_like(L: int, g: np.random.Generator, scale_events: bool = True) -> np.
             continue
         t = np.arange(n) / FS
         x[i0:i0 + n] += amp * np.exp(-t / tau) * np.sin(2 * np.pi * f * t + g.uniform(0, 2 * np.pi))
-    # pink noise, 30 dB below the deterministic part
-    wn = g.standard_normal(L)
-    X = np.fft.rfft(wn)
+    # pink noise, 30 dB below the deterministic part: white noise shaped by
+    # 1/sqrt(f) on the next power-of-two length, truncated to L
+    nf = 1 << int(np.ceil(np.log2(L)))
+    X = np.fft.rfft(g.standard_normal(nf))
     f = np.arange(len(X), dtype=np.float64)
     f[0] = 1.0
     X /= np.sqrt(f)
     X[0] = 0.0
-    pn = np.fft.irfft(X, n=L)
+    pn = np.fft.irfft(X, n=nf)[:L]
     ed = float(np.sum(x * x))
     if ed <= 0.0:
         ed = float(L)

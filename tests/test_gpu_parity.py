@@ -198,3 +198,24 @@ def test_resynth_and_coefs():
             if a["w"] == w:
                 ref[a["n"], a["m"]] += a["re"] + 1j * a["im"]
         assert np.max(np.abs(c - ref)) < 1e-14 * max(1.0, np.abs(ref).max())
+
+
+def test_fresh_plan_after_freed_plans():
+    # padding leaves must read as empty even when the allocator hands back
+    # memory that earlier plans wrote
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 64, 16, 64), (0, 256, 64, 256)]
+    junk = []
+    for i in range(3):
+        x = np.random.default_rng(100 + i).standard_normal(8192)
+        p = mpg.Plan(dicts, [8192], 1e-4, F64)
+        p.analyze(torch.from_numpy(x).cuda())
+        p.run(50)
+        junk.append(p)
+    del junk
+    import gc
+    gc.collect()
+    x = np.random.default_rng(7).standard_normal(4096)
+    _, ga = gpu_run(dicts, [x], 1e-4, K=200, flags=F64)
+    assert_identical(ga[0], oracle_run(dicts, x, 1e-4, K=200))
