@@ -75,7 +75,12 @@ def main():
                     help="the CPU oracle runs the first signals of the batch until this many samples "
                          "are covered (0: skip)")
     ap.add_argument("--fp64-sample", type=int, default=4, help="signals run on the plain FP64 GPU path")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.calib_copy > 0:
+        calib_copy(args.calib_copy)
+        return
     if args.gpus != 1:
         sys.stderr.write("bench.py measures one GPU only: this build runs on a single MI355X and has "
                          "no multi-GPU path (signals would shard across GPUs with no exchange). "
@@ -225,6 +230,19 @@ def main():
         "counters": {"updated": int(st.updated), "blocks": int(st.blocks), "groups": int(st.l1_groups)},
     }
     print(json.dumps(out))
+
+
+def calib_copy(nbytes):
+    """A plain device-to-device copy of known size: reading nbytes and writing
+    nbytes, to scale the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": n * 4, "launches": 3}))
 
 
 def _kernel_sha():
