@@ -28,7 +28,7 @@ hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, in
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
                       const void* win, const void* tw, void* planes, void* leaves, hipStream_t st);
 size_t leaf_bytes(bool f64);
-size_t mp_shmem_bytes(bool f64, int nt, int n_groups_max, bool preload);
+size_t mp_shmem_bytes(bool f64, int nt, int G, int n_groups_max);
 hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st);
 hipError_t launch_resynth(const AtomRec* atoms, const SigState* st_, const DictDev* dicts,
                           const double* win64, int64_t Lp, double* acc, void* y, int dtype,
@@ -314,21 +314,54 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       q = q / gcd64(q, dicts[w].M) * dicts[w].M;
       for (int v = 0; v < W; ++v) need = std::max<int64_t>(need, dicts[w].gl + dicts[v].gl);
     }
-    // tree group size: keep the per-workgroup group nodes within 32 KiB of LDS
+    // tree group size.  FP64: keep the group nodes within 32 KiB of LDS.
+    // FP32: 256 leaves (128 on request through MPG_GL=128) if the group keys
+    // fit the LDS.
     {
-      const size_t node = p->f64 ? 32 : 16;
-      int64_t maxl = 0;
-      for (int s = 0; s < batch; ++s) {
-        const int64_t Lp = (L[s] + q - 1) / q * q;
-        int64_t c = 0;
-        for (int w = 0; w < W; ++w) c += (Lp / dicts[w].a) * ((dicts[w].M / 2 + 1 + ROW - 1) / ROW);
-        maxl = std::max(maxl, c);
-      }
-      p->G = GLEAVES;
-      p->logG = 8;
-      while ((size_t)((maxl + p->G - 1) / p->G + W) * node > 32 * 1024) {
-        p->G *= 2;
-        p->logG += 1;
+      auto groups_max = [&](int G) {
+        int64_t m = 0;
+        for (int s = 0; s < batch; ++s) {
+          const int64_t Lp = (L[s] + q - 1) / q * q;
+          int64_t c = 0;
+          for (int w = 0; w < W; ++w)
+            c += ((Lp / dicts[w].a) * ((dicts[w].M / 2 + 1 + ROW - 1) / ROW) + G - 1) / G;
+          m = std::max(m, c);
+        }
+        return m;
+      };
+      if (p->f64) {
+        const size_t node = 32;
+        int64_t maxl = 0;
+        for (int s = 0; s < batch; ++s) {
+          const int64_t Lp = (L[s] + q - 1) / q * q;
+          int64_t c = 0;
+          for (int w = 0; w < W; ++w) c += (Lp / dicts[w].a) * ((dicts[w].M / 2 + 1 + ROW - 1) / ROW);
+          maxl = std::max(maxl, c);
+        }
+        p->G = GLEAVES;
+        p->logG = 8;
+        while ((size_t)((maxl + p->G - 1) / p->G + W) * node > 32 * 1024) {
+          p->G *= 2;
+          p->logG += 1;
+        }
+      } else {
+        p->G = 0;
+        int gpref = 256;
+        if (const char* e = getenv("MPG_GL"))
+          if (atoi(e) == 128) gpref = 128;
+        for (int G : {128, 256}) {
+          if (G < gpref) continue;
+          const int64_t ng = groups_max(G);
+          if (ng < (1 << 24) && mp_shmem_bytes(false, 512, G, (int)ng) <= 160 * 1024) {
+            p->G = G;
+            p->logG = G == 128 ? 7 : 8;
+            break;
+          }
+        }
+        if (!p->G) {
+          rc = MP_E_LIMIT;
+          goto fail;
+        }
       }
     }
     p->hs.resize(batch);
@@ -603,8 +636,8 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       const int v = atoi(e);
       if (v == 256 || v == 512) p->nt = v;
     }
-    p->shmem = mp_shmem_bytes(p->f64, p->nt, p->n_groups_max, p->G == GLEAVES);
-    if (p->shmem > 160 * 1024) {
+    p->shmem = mp_shmem_bytes(p->f64, p->nt, p->G, p->n_groups_max);
+    if (p->shmem == 0 || p->shmem > 160 * 1024) {
       rc = MP_E_LIMIT;
       goto fail;
     }

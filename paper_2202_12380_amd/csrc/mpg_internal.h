@@ -8,7 +8,7 @@ namespace mpg {
 constexpr int MAXW = 8;        // Gabor systems per plan
 constexpr int ROW = 16;        // coefficients per max-tree leaf (one DPP row)
 constexpr int LOG_ROW = 4;
-constexpr int GLEAVES = 256;   // leaves per group when the group preload path is used
+constexpr int GLEAVES = 256;   // leaves per group when the group preload path is used (FP64)
 
 // One Gabor system.
 struct DictDev {

@@ -84,13 +84,13 @@ struct KeyOps<double> {
   }
 };
 
-// A leaf / tree node: key of the block maximum and the complex value there.
+// A leaf of the max tree.  FP32: the key alone.  FP64: the key and the
+// complex value there.
 template <typename R>
 struct Leaf;
 template <>
-struct __align__(16) Leaf<float> {
+struct __align__(8) Leaf<float> {
   uint64_t key;
-  float re, im;
 };
 template <>
 struct __align__(16) Leaf<double> {
@@ -101,11 +101,9 @@ struct __align__(16) Leaf<double> {
 
 __device__ __forceinline__ uint64_t leaf_key(const Leaf<float>& l) { return l.key; }
 __device__ __forceinline__ Key96 leaf_key(const Leaf<double>& l) { return Key96{l.v, l.n}; }
-__device__ __forceinline__ Leaf<float> make_leaf(uint64_t k, float re, float im) {
+__device__ __forceinline__ Leaf<float> make_leaf(uint64_t k, float, float) {
   Leaf<float> l;
   l.key = k;
-  l.re = re;
-  l.im = im;
   return l;
 }
 __device__ __forceinline__ Leaf<double> make_leaf(Key96 k, double re, double im) {
@@ -1032,6 +1030,495 @@ __global__ void __launch_bounds__(NT) k_mp(MPArgs A) {
   }
 }
 
+// --------------------------------------------------------------------------
+// FP32 MP loop.  Same selection / adjustment / update as above; the tree is
+// kept differently:
+//   leaves (16 bins of one frame, 8-byte keys, global memory)
+//     -> groups of GL leaves (keys in LDS) -> root (reduced per selection).
+// A touched group whose maximum leaf lies outside the update grid can only
+// gain from the update, so the row leaders raise its key with an LDS atomic
+// maximum.  A group whose maximum leaf is rewritten ("dirty", always the
+// group of the selected atom) is re-reduced after the update: its old leaves
+// are preloaded into registers while the rows are processed, the rewritten
+// ones go through an LDS scratch, and the owner wave merges the two.
+//
+// Per selection: wave 0 (root, decode, target grids, dirty groups) | barrier |
+// all waves (rows: loads, adjustment, update, leaves) | barrier | owners merge
+// dirty groups | barrier.
+
+constexpr uint64_t KEY_SENT = ~0ull;     // scratch entry not written
+
+// Row geometry of one target system for the current selection (LDS).  All M
+// and a are powers of two, so r_w and a_w / a_min are shifts.
+struct __align__(16) RowT {
+  int32_t MR, N, off, lbase;
+  int32_t lpf, nlo, nF, ilo;
+  int32_t bpf, item_base, rsh, mm;   // r_w = 1 << rsh, mm = M_max - 1
+  int32_t k1, k2, mspan, hrow0;      // term 1 in the box iff ((m r_w - k1) & mm) <= mspan, term 2 with k2
+  int32_t hstep, slot_base;          // table row of frame f: hrow0 + f hstep; first touched-group slot
+  uint32_t ph0, phs;                 // phase index of frame f: (ph0 + f phs) mod M_v
+  int32_t gA_lo, gA_n, gB_lo, gB_n;  // touched groups (run A: frames from nlo, run B: wrapped)
+  float rbpf;                        // 1 / bpf
+  int32_t pad[3];
+};
+
+// Per-selection values shared by all waves (written by wave 0).
+struct __align__(16) It32 {
+  int32_t p, v, kk, j;
+  int32_t pair, T_items, TG, stop;
+  int32_t root_off, vmask, partner, pad;
+  Cx<float> cc;                      // adjusted coefficient c~ of the selected atom (pair)
+  double Et;                         // energy decrease of the selection
+  int32_t ibase[MAXW];               // first row item of each target
+  int32_t sbase[MAXW];               // first touched-group slot of each target
+};
+
+__host__ __device__ constexpr int mp32_groups_padded(int n_groups) { return (n_groups + 511) & ~511; }
+
+template <int NT, int GL>
+__host__ __device__ constexpr size_t mp32_lds_bytes(int n_groups_max) {
+  return (size_t)mp32_groups_padded(n_groups_max) * 8 + (size_t)(2 * (NT / 64)) * GL * 8 +
+         (size_t)MAXW * sizeof(RowT) + (size_t)MAXW * MAXW * sizeof(PairC) + sizeof(It32) + 64;
+}
+
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+template <int NT, int SLOTS, int GL>
+__device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lane, int wave) {
+  constexpr int NW = NT / 64;
+  constexpr int LPL = GL / 64;                 // leaves of a group per lane
+  constexpr int LOG_GL = GL == 128 ? 7 : 8;
+  constexpr int NPRE = 2 * NW;                 // touched groups merged from registers + LDS scratch
+  static_assert(GL == 128 || GL == 256, "group size");
+  const SigDev& S = A.sigs[s];
+  const int W = A.W;
+  const int n_groups = S.n_groups;
+  const int ngp = mp32_groups_padded(n_groups);
+  const int ngp_max = mp32_groups_padded(A.n_groups_max);
+  Cx<float>* rho = reinterpret_cast<Cx<float>*>(A.planes) + S.coef_base;
+  uint64_t* leaves = reinterpret_cast<uint64_t*>(A.leaves) + S.leaf_base;
+  const Cx<float>* tabs = reinterpret_cast<const Cx<float>*>(A.tabs);
+  const Cx<float>* gams = reinterpret_cast<const Cx<float>*>(A.gammas);
+  const Cx<float>* roots = reinterpret_cast<const Cx<float>*>(A.roots);
+  const int rid = lane >> LOG_ROW, rl = lane & (ROW - 1);
+
+  // LDS carve-up (must match mp32_lds_bytes)
+  uint64_t* gkey = reinterpret_cast<uint64_t*>(smem);
+  uint64_t* scratch = gkey + ngp_max;
+  RowT* tg = reinterpret_cast<RowT*>(scratch + NPRE * GL);
+  PairC* pc = reinterpret_cast<PairC*>(tg + MAXW);
+  It32* it = reinterpret_cast<It32*>(pc + MAXW * MAXW);
+
+  // ---- per-signal constants, group maxima, scratch reset ----
+  for (int t = threadIdx.x; t < W * W; t += NT) {
+    const int w = t / W;
+    const PairDev P = A.pairs[t];
+    const DictDev Dw = A.dicts[w];
+    PairC c;
+    c.MR = Dw.MR; c.N = S.N[w]; c.off = (int)S.off[w]; c.lbase = (int)S.lbase[w];
+    c.lpf = Dw.lpf; c.Mmax = P.Mmax; c.rw = P.rw; c.rv = P.rv;
+    c.dbox = P.dbox; c.mulo = P.mu_lo; c.muhi = P.mu_hi; c.width = P.width;
+    c.sw = P.sw; c.sv = P.sv; c.Lpa = 0; c.amin = P.amin;
+    c.M = Dw.M;
+    c.sw_sh = 31 - __clz(P.sw);
+    c.rw_sh = 31 - __clz(P.rw);
+    c.pad = 0;
+    c.tab = P.tab_off;
+    c.pad2[0] = c.pad2[1] = 0;
+    pc[t] = c;
+  }
+  // dictionary constants, lane u < W holds system u
+  int d_off = 0x7fffffff, d_MR = 1, d_M = 2, d_sh = 0, d_gam = 0, d_root = 0;
+  uint32_t d_mul = 0;
+  if (lane < W) {
+    const DictDev D = A.dicts[lane];
+    d_off = (int)S.off[lane];
+    d_MR = D.MR;
+    d_M = D.M;
+    d_sh = D.mr_sh;
+    d_mul = D.mr_mul;
+    d_gam = (int)D.gamma_off;
+    d_root = (int)D.root_off;
+  }
+  for (int g = wave; g < ngp; g += NW) {
+    uint64_t best = 0ull;
+    if (g < n_groups) {
+#pragma unroll
+      for (int x = 0; x < LPL; ++x) best = umax64(best, leaves[g * GL + lane + 64 * x]);
+    }
+    const uint64_t wm = wave_max_key2<float>(best);
+    if (lane == 0) gkey[g] = wm;
+  }
+  for (int i = threadIdx.x; i < NPRE * GL; i += NT) scratch[i] = KEY_SENT;
+  __syncthreads();
+
+  SigState st = A.state[s];
+  double E = st.E;
+  int64_t k = st.k;
+  const double E0 = st.E0;
+  int64_t K = A.K > 0 ? A.K : S.Lp / 5;
+  if (K > S.cap) K = S.cap;
+  const double Etarget = A.snr_db > 0.0 ? E0 * exp10(-A.snr_db / 10.0) : -__builtin_huge_val();
+  int stop = 0;
+  int64_t c_upd = 0, c_blk = 0, c_grp = 0;
+
+  for (;;) {
+    if (k >= K) { stop = 1; break; }
+    if (E <= Etarget) { stop = 2; break; }
+    if (E < 0.0) { stop = 3; break; }
+
+    // ---- wave 0: root, decode, target grids, adjustment ----
+    if (wave == 0) {
+      uint64_t best = 0ull;
+      for (int i0 = 0; i0 < ngp; i0 += 512) {
+        const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(gkey + i0);
+        const ulonglong2 a = g2[lane], b = g2[lane + 64], c = g2[lane + 128], d = g2[lane + 192];
+        best = umax64(best, umax64(umax64(umax64(a.x, a.y), umax64(b.x, b.y)),
+                                   umax64(umax64(c.x, c.y), umax64(d.x, d.y))));
+      }
+      const uint64_t bk = wave_max_key2<float>(best);
+      if ((uint32_t)(bk >> 32) == 0u) {  // max |rho|^2 is zero
+        if (lane == 0) it->stop = 1;
+      } else {
+        const int p = uni_i((int)~(uint32_t)bk);
+        const int v = uni_i(__popcll(__ballot(lane < W && p >= d_off)) - 1);
+        const int off_v = (int)rdlane32((uint32_t)d_off, v), MR_v = (int)rdlane32((uint32_t)d_MR, v);
+        const int M_v = (int)rdlane32((uint32_t)d_M, v), sh_v = (int)rdlane32((uint32_t)d_sh, v);
+        const uint32_t mul_v = rdlane32(d_mul, v);
+        const int q0 = p - off_v;
+        const int j = magic_div(q0, mul_v, sh_v);
+        const int kk = q0 - j * MR_v;
+        const bool pair = kk != 0 && 2 * kk != M_v;
+        const int vmask = M_v - 1;
+        // rho(p) and gamma, consumed at the end of this phase (no row is
+        // rewritten before the barrier)
+        const Cx<float> rp = rho[p];
+        const Cx<float> gam = gams[(int)rdlane32((uint32_t)d_gam, v) + (pair ? kk : 0)];
+
+        // geometry of target u = lane (all lanes compute; lanes >= W are discarded)
+        const int u = lane < W ? lane : 0;
+        const PairC P = pc[u * W + v];
+        RowT T;
+        T.MR = P.MR; T.N = P.N; T.off = P.off; T.lbase = P.lbase; T.lpf = P.lpf;
+        const int kr = kk * P.rv;
+        T.rsh = P.rw_sh;
+        T.mm = P.Mmax - 1;
+        T.k1 = kr + P.mulo;
+        T.k2 = P.mulo - kr;
+        T.mspan = P.muhi - P.mulo;
+        T.pad[0] = T.pad[1] = T.pad[2] = 0;
+        const int jsv = j * P.sv;
+        const int nlo = -((P.dbox - jsv) >> P.sw_sh), nhi = (jsv + P.dbox) >> P.sw_sh;
+        const int half = P.M >> 1;
+        // bins m in [0, M/2] with m r_w in +-k r_v + [mu_lo, mu_hi] (mod M_max)
+        int mlo = 1 << 30, mhi = -1;
+#pragma unroll
+        for (int term = 0; term < 2; ++term) {
+          const int base = term == 0 ? kr : -kr;
+          const int A1 = -((-(base + P.mulo)) >> P.rw_sh), B1 = (base + P.muhi) >> P.rw_sh;
+          const bool use = term == 0 || pair;
+          const bool full = B1 - A1 + 1 >= P.M;
+#pragma unroll
+          for (int c = -1; c <= 1; ++c) {
+            const int lo = full ? 0 : max(A1 + c * P.M, 0), hi = full ? half : min(B1 + c * P.M, half);
+            const bool ok = use && lo <= hi;
+            mlo = ok ? min(mlo, lo) : mlo;
+            mhi = ok ? max(mhi, hi) : mhi;
+          }
+        }
+        const bool valid = lane < W && P.dbox >= 0 && mhi >= 0 && nhi >= nlo;
+        const int nl = nlo < 0 ? nlo + P.N : (nlo >= P.N ? nlo - P.N : nlo);
+        T.nlo = nl;
+        T.nF = valid ? nhi - nlo + 1 : 0;
+        const int dlo = nlo * P.sw - jsv;  // delta of the first frame, in [-dbox, dbox]
+        T.ilo = valid ? mlo >> LOG_ROW : 0;
+        T.bpf = valid ? (mhi >> LOG_ROW) - T.ilo + 1 : 1;
+        T.rbpf = 1.0f / (float)T.bpf;
+        T.hrow0 = (int)P.tab + (dlo + P.dbox) * P.width;
+        T.hstep = P.width * P.sw;
+        const uint32_t cph = (uint32_t)(kk * P.amin) & (uint32_t)vmask;
+        T.ph0 = (uint32_t)dlo * cph;
+        T.phs = cph * (uint32_t)P.sw;
+        const int t_items = valid ? ((T.nF * T.bpf) + 3) & ~3 : 0;
+        const int ihi = mhi >> LOG_ROW;
+        const int nend = T.nlo + T.nF - 1;
+        const int nAe = min(nend, T.N - 1);
+        T.gA_lo = (T.lbase + T.nlo * T.lpf + T.ilo) >> LOG_GL;
+        T.gA_n = valid ? ((T.lbase + nAe * T.lpf + ihi) >> LOG_GL) - T.gA_lo + 1 : 0;
+        T.gB_lo = (T.lbase + T.ilo) >> LOG_GL;
+        const int gBhi = min((T.lbase + (nend - T.N) * T.lpf + ihi) >> LOG_GL, T.gA_lo - 1);
+        T.gB_n = (valid && nend >= T.N) ? max(0, gBhi - T.gB_lo + 1) : 0;
+        const int t_groups = T.gA_n + T.gB_n;
+        int ib = 0, sb = 0;
+        for (int w = 0; w + 1 < W; ++w) {
+          const int iw = (int)rdlane32((uint32_t)t_items, w), gw = (int)rdlane32((uint32_t)t_groups, w);
+          ib += w < lane ? iw : 0;
+          sb += w < lane ? gw : 0;
+        }
+        T.item_base = ib;
+        T.slot_base = sb;
+        // cross-lane reads with the whole wave active
+        const int T_items = (int)rdlane32((uint32_t)(ib + t_items), W - 1);
+        const int TG = (int)rdlane32((uint32_t)(sb + t_groups), W - 1);
+        const int root_v = (int)rdlane32((uint32_t)d_root, v);
+        if (lane < W) {
+          tg[lane] = T;
+          it->ibase[lane] = ib;
+          it->sbase[lane] = sb;
+        }
+        // coefficient adjustment for the pair, Eq. (dualatprod), and energy
+        // decrease, Eq. (projenfaster)
+        Cx<float> cc;
+        double Et;
+        bool partner = false;
+        {
+          const float rr = rp.re, ri = rp.im;
+          if (pair) {
+            const float gr = gam.re, gi = gam.im;
+            const float nr = rr - (gr * rr - gi * ri);
+            const float ni = ri - (-gr * ri - gi * rr);
+            const float den = 1.0f - (gr * gr + gi * gi);
+            cc.re = nr / den;
+            cc.im = ni / den;
+            const double cr = cc.re, ci = cc.im, dgr = gr, dgi = gi;
+            Et = 2.0 * (cr * cr + ci * ci + dgr * (cr * cr - ci * ci) - 2.0 * dgi * cr * ci);
+            partner = A.partner_gate ? (gr != 0.0f || gi != 0.0f) : true;
+          } else {
+            cc.re = rr;
+            cc.im = ri;
+            const double cr = cc.re, ci = cc.im;
+            Et = cr * cr + ci * ci;
+          }
+        }
+        if (lane == 0) {
+          int4* I = reinterpret_cast<int4*>(&it->p);
+          I[0] = make_int4(p, v, kk, j);
+          I[1] = make_int4(pair, T_items, TG, 0);
+          I[2] = make_int4(root_v, vmask, partner, 0);
+          it->cc = cc;
+          it->Et = Et;
+          AtomRec ar;
+          ar.w = v;
+          ar.m = kk;
+          ar.n = j;
+          ar.pad = 0;
+          ar.re = (double)cc.re;
+          ar.im = (double)cc.im;
+          ar.E_after = E - Et;
+          A.atoms[S.atom_base + k] = ar;
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const int istop = uni_i(it->stop);
+      if (istop) {
+        stop = 4;
+        break;
+      }
+    }
+    const int4 I0 = *reinterpret_cast<const int4*>(&it->p);
+    const int4 I1 = *reinterpret_cast<const int4*>(&it->pair);
+    const int4 I2 = *reinterpret_cast<const int4*>(&it->root_off);
+    const Cx<float> cc = it->cc;
+    const double Et = it->Et;
+    const int ibase = lane < W ? it->ibase[lane] : 0x7fffffff;
+    const int sbase = lane < W ? it->sbase[lane] : 0x7fffffff;
+    const int p = uni_i(I0.x);
+    const bool pair = uni_i(I1.x) != 0;
+    const int T_items = uni_i(I1.y), TG = uni_i(I1.z);
+    const uint32_t root_off = (uint32_t)uni_i(I2.x);
+    const uint32_t vmask = (uint32_t)uni_i(I2.y);
+    const bool partner = uni_i(I2.z) != 0;
+    E -= Et;
+    ++k;
+
+    // touched-group slots this wave merges: gs = wave and wave + NW
+    const int gs0 = wave, gs1 = wave + NW;
+    int g0 = 0, g1 = 0;
+    {
+      const int w0 = uni_i(__popcll(__ballot(sbase <= gs0)) - 1);
+      const int w1 = uni_i(__popcll(__ballot(sbase <= gs1)) - 1);
+      const int4 a0 = *reinterpret_cast<const int4*>(&tg[w0].gA_lo);
+      const int sb0 = tg[w0].slot_base;
+      const int4 a1 = *reinterpret_cast<const int4*>(&tg[w1].gA_lo);
+      const int sb1 = tg[w1].slot_base;
+      const int c0 = gs0 - sb0, c1 = gs1 - sb1;
+      g0 = uni_i(c0 < a0.y ? a0.x + c0 : a0.z + (c0 - a0.y));
+      g1 = uni_i(c1 < a1.y ? a1.x + c1 : a1.z + (c1 - a1.y));
+    }
+    // preload their old leaves
+    uint64_t old0[LPL], old1[LPL];
+    if (gs0 < TG) {
+#pragma unroll
+      for (int x = 0; x < LPL; ++x) old0[x] = leaves[(uint32_t)(g0 * GL + lane + 64 * x)];
+    }
+    if (gs1 < TG) {
+#pragma unroll
+      for (int x = 0; x < LPL; ++x) old1[x] = leaves[(uint32_t)(g1 * GL + lane + 64 * x)];
+    }
+
+    // ---- rows of the target grids: loads, update, new leaves ----
+    const int nslots = T_items >> 2;
+    const int chunk = (nslots + NW - 1) / NW;
+    const int q_begin = wave * chunk, q_end = min(nslots, q_begin + chunk);
+    for (int qb = q_begin; qb < q_end; qb += SLOTS) {
+      const int nact = min(SLOTS, q_end - qb);
+      Cx<float> r[SLOTS], h1[SLOTS], h2[SLOTS], ph[SLOTS];
+      uint32_t ee[SLOTS], lfi[SLOTS], fl[SLOTS];  // fl bit 0: row in grid, 1: bin valid, 2/3: term 1/2 in box
+      int gsl[SLOTS];
+      {
+        int cw = -1;
+        RowT T;
+#pragma unroll
+        for (int sl = 0; sl < SLOTS; ++sl) {
+          if (sl >= nact) break;  // wave-uniform
+          const int base4 = (qb + sl) * 4;
+          const int w = uni_i(__popcll(__ballot(ibase <= base4)) - 1);
+          if (w != cw) {
+            T = tg[w];
+            cw = w;
+          }
+          // row t of target w's grid: frame f, 16-bin block i
+          const int t = base4 - T.item_base + rid;
+          int f = (int)((float)t * T.rbpf);
+          f -= f * T.bpf > t ? 1 : 0;
+          f += (f + 1) * T.bpf <= t ? 1 : 0;
+          const int i = T.ilo + t - f * T.bpf;
+          const bool ok = f < T.nF;
+          int n = T.nlo + f;
+          n -= n >= T.N ? T.N : 0;
+          const int li = T.lbase + n * T.lpf + i;
+          const int m = (i << LOG_ROW) + rl;
+          const bool vl = ok && m < T.MR;
+          const uint32_t e = (uint32_t)(T.off + n * T.MR + m);
+          const uint32_t hrow = (uint32_t)(T.hrow0 + f * T.hstep);
+          const uint32_t u1 = (uint32_t)((m << T.rsh) - T.k1) & (uint32_t)T.mm;
+          const uint32_t u2 = (uint32_t)((m << T.rsh) - T.k2) & (uint32_t)T.mm;
+          const bool in1 = vl && u1 <= (uint32_t)T.mspan;
+          const bool in2 = vl && pair && u2 <= (uint32_t)T.mspan;
+          // every lane loads (out-of-grid lanes from valid stand-in addresses)
+          r[sl] = rho[vl ? e : (uint32_t)p];
+          h1[sl] = tabs[in1 ? hrow + u1 : 0u];
+          h2[sl] = tabs[in2 ? hrow + u2 : 0u];
+          ph[sl] = roots[root_off + ((T.ph0 + (uint32_t)f * T.phs) & vmask)];
+          ee[sl] = e;
+          lfi[sl] = (uint32_t)li;
+          fl[sl] = (ok ? 1u : 0u) | (vl ? 2u : 0u) | (in1 ? 4u : 0u) | (in2 ? 8u : 0u);
+          // touched-group slot of the row's group
+          const int g = li >> LOG_GL;
+          gsl[sl] = T.slot_base + ((g >= T.gA_lo && g < T.gA_lo + T.gA_n) ? g - T.gA_lo : T.gA_n + g - T.gB_lo);
+        }
+      }
+#pragma unroll
+      for (int sl = 0; sl < SLOTS; ++sl) {
+        if (sl >= nact) break;  // wave-uniform
+        const uint32_t fs = fl[sl];
+        const Cx<float> a1 = (fs & 4u) ? h1[sl] : Cx<float>{0.0f, 0.0f};
+        const Cx<float> b2 = ((fs & 8u) && partner) ? h2[sl] : Cx<float>{0.0f, 0.0f};
+        const bool nz = (a1.re != 0.0f) | (a1.im != 0.0f) | (b2.re != 0.0f) | (b2.im != 0.0f);
+        const float cs = ph[sl].re, sn = ph[sl].im;
+        // c (h1 phi) + conj(c) (h2 conj(phi))
+        const float ar = a1.re * cs - a1.im * sn, ai = a1.re * sn + a1.im * cs;
+        float ur = cc.re * ar - cc.im * ai, ui = cc.re * ai + cc.im * ar;
+        const float br = b2.re * cs + b2.im * sn, bi = b2.im * cs - b2.re * sn;
+        ur += cc.re * br + cc.im * bi;
+        ui += cc.re * bi - cc.im * br;
+        Cx<float> rv = r[sl];
+        rv.re -= ur;
+        rv.im -= ui;
+        if (nz) rho[ee[sl]] = rv;
+        const bool vl = (fs & 2u) != 0;
+        const float val = rv.re * rv.re + rv.im * rv.im;
+        const uint32_t bits = vl ? __float_as_uint(val) : 0u;
+        const uint32_t rm = (uint32_t)row_max_bits<float>(bits);
+        const uint64_t bal = __ballot(vl && bits == rm);
+        const uint32_t rowbits = (uint32_t)(bal >> (rid * ROW)) & 0xFFFFu;
+        const bool leader = (fs & 1u) && rowbits && lane == rid * ROW + __ffs(rowbits) - 1;
+        c_upd += __popcll(__ballot(nz));
+        c_blk += __popcll(__ballot(leader));
+        if (leader) {
+          const uint64_t key = ((uint64_t)bits << 32) | (uint64_t)(~ee[sl]);
+          const uint32_t b = lfi[sl];
+          leaves[b] = key;
+          if (gsl[sl] < NPRE) scratch[gsl[sl] * GL + (b & (GL - 1))] = key;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- touched groups: merge old and rewritten leaves ----
+    if (gs0 < TG) {
+      uint64_t best = 0ull;
+#pragma unroll
+      for (int x = 0; x < LPL; ++x) {
+        uint64_t& sc = scratch[gs0 * GL + lane + 64 * x];
+        const uint64_t scv = sc;
+        const bool w_ = scv != KEY_SENT;
+        if (w_) sc = KEY_SENT;
+        best = umax64(best, w_ ? scv : old0[x]);
+      }
+      const uint64_t wm = wave_max_key2<float>(best);
+      if (lane == 0) gkey[g0] = wm;
+      ++c_grp;
+    }
+    if (gs1 < TG) {
+      uint64_t best = 0ull;
+#pragma unroll
+      for (int x = 0; x < LPL; ++x) {
+        uint64_t& sc = scratch[gs1 * GL + lane + 64 * x];
+        const uint64_t scv = sc;
+        const bool w_ = scv != KEY_SENT;
+        if (w_) sc = KEY_SENT;
+        best = umax64(best, w_ ? scv : old1[x]);
+      }
+      const uint64_t wm = wave_max_key2<float>(best);
+      if (lane == 0) gkey[g1] = wm;
+      ++c_grp;
+    }
+    // slots beyond the preloaded ones: the leaves in global memory are current
+    for (int gs = NPRE + wave; gs < TG; gs += NW) {
+      const int w = uni_i(__popcll(__ballot(sbase <= gs)) - 1);
+      const int4 a = *reinterpret_cast<const int4*>(&tg[w].gA_lo);
+      const int c = gs - tg[w].slot_base;
+      const int g = uni_i(c < a.y ? a.x + c : a.z + (c - a.y));
+      uint64_t best = 0ull;
+#pragma unroll
+      for (int x = 0; x < LPL; ++x) best = umax64(best, leaves[(uint32_t)(g * GL + lane + 64 * x)]);
+      const uint64_t wm = wave_max_key2<float>(best);
+      if (lane == 0) gkey[g] = wm;
+      ++c_grp;
+    }
+    __syncthreads();
+  }
+
+  if (lane == 0) {
+    atomicAdd((unsigned long long*)&A.state[s].updated, (unsigned long long)c_upd);
+    atomicAdd((unsigned long long*)&A.state[s].blocks, (unsigned long long)c_blk);
+    atomicAdd((unsigned long long*)&A.state[s].groups, (unsigned long long)c_grp);
+  }
+  if (wave == 0 && lane == 0) {
+    A.state[s].E = E;
+    A.state[s].k = k;
+    A.state[s].stop = stop;
+  }
+}
+
+template <int NT, int SLOTS, int GL>
+__global__ void __launch_bounds__(NT) k_mp32(MPArgs A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_next;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(A.queue, 1);
+    __syncthreads();
+    const int qi = s_next;
+    __syncthreads();
+    if (qi >= A.batch) break;
+    mp_signal32<NT, SLOTS, GL>(A, A.order[qi], smem_raw, lane, wave);
+  }
+}
+
 __global__ void k_fill_i32(int32_t* p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1195,22 +1682,45 @@ static hipError_t launch_mp_t(const MPArgs& a, int grid, bool preload, hipStream
   return hipGetLastError();
 }
 
-size_t mp_shmem_bytes(bool f64, int nt, int n_groups_max, bool preload) {
-  if (f64) return nt == 256 ? mp_lds_bytes<double, 256, 4>(n_groups_max, preload) : mp_lds_bytes<double, 512, 4>(n_groups_max, preload);
-  if (nt == 256) return mp_lds_bytes<float, 256, 6>(n_groups_max, preload);
-  return mp_lds_bytes<float, 512, 6>(n_groups_max, preload);
+template <int NT, int SLOTS, int GL>
+static hipError_t launch_mp32_t(const MPArgs& a, int grid, hipStream_t st) {
+  const size_t sh = mp32_lds_bytes<NT, GL>(a.n_groups_max);
+  if (sh > 160 * 1024) return hipErrorInvalidValue;
+  (void)hipFuncSetAttribute((const void*)k_mp32<NT, SLOTS, GL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sh);
+  k_mp32<NT, SLOTS, GL><<<grid, NT, sh, st>>>(a);
+  return hipGetLastError();
+}
+
+// LDS bytes of the MP kernel for the launch shape (0: unsupported shape).
+size_t mp_shmem_bytes(bool f64, int nt, int G, int n_groups_max) {
+  if (f64) {
+    const bool preload = G == GLEAVES;
+    return nt == 256 ? mp_lds_bytes<double, 256, 4>(n_groups_max, preload)
+                     : mp_lds_bytes<double, 512, 4>(n_groups_max, preload);
+  }
+  if (G == 128) return nt == 256 ? mp32_lds_bytes<256, 128>(n_groups_max) : mp32_lds_bytes<512, 128>(n_groups_max);
+  if (G == 256) return nt == 256 ? mp32_lds_bytes<256, 256>(n_groups_max) : mp32_lds_bytes<512, 256>(n_groups_max);
+  return 0;
 }
 
 hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st) {
   k_fill_i32<<<1, 64, 0, st>>>(a.queue, 1, 0);
   CHK(hipGetLastError());
-  const bool preload = a.G == GLEAVES;
   if (f64) {
+    const bool preload = a.G == GLEAVES;
     if (nt == 256) return launch_mp_t<double, 256, 4>(a, grid, preload, st);
     return launch_mp_t<double, 512, 4>(a, grid, preload, st);
   }
-  if (nt == 256) return launch_mp_t<float, 256, 6>(a, grid, preload, st);
-  return launch_mp_t<float, 512, 6>(a, grid, preload, st);
+  if (a.G == 128) {
+    if (nt == 256) return launch_mp32_t<256, 6, 128>(a, grid, st);
+    return launch_mp32_t<512, 6, 128>(a, grid, st);
+  }
+  if (a.G == 256) {
+    if (nt == 256) return launch_mp32_t<256, 6, 256>(a, grid, st);
+    return launch_mp32_t<512, 6, 256>(a, grid, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_resynth(const AtomRec* atoms, const SigState* st_, const DictDev* dicts, const double* win64,
