@@ -30,7 +30,7 @@ from paper_2202_12380_amd import signals as S  # noqa: E402
 HBM_PEAK_GBPS = 8000.0
 SNR_DB = 40.0
 K_CAP = 1 << 17
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mp_f32_c3_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mp32_f32_c3_traffic.json")
 
 
 def log(msg):
@@ -218,7 +218,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "k_mp<float,512>", "alg_bytes_per_launch": alg_bytes,
+                     "kernel": "mpg::k_mp32<%d, 6, %d>" % (st.threads, st.group_leaves), "alg_bytes_per_launch": alg_bytes,
                      "launch_ms": loop_ms},
         "cpu_baseline": cpu,
         "mp_loop_atoms_per_s": loop_rate,

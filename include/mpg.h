@@ -108,11 +108,13 @@ typedef struct {
 typedef struct {
   int64_t atoms;          /* selections in the last mp_run, over the batch  */
   int64_t updated;        /* coefficient updates with a nonzero kernel entry */
-  int64_t blocks;         /* 64-coefficient blocks read and rescanned       */
+  int64_t blocks;         /* max-tree leaves (16 bins of a frame) rewritten  */
   int64_t l1_groups;      /* tree groups recomputed                          */
   double loop_ms;         /* device time of the last mp_run's MP kernel     */
   double analyze_ms;      /* device time of the last mp_analyze             */
   double dgt_ms;          /* device time of the DGT kernels in it           */
+  int32_t group_leaves;   /* leaves per tree group of the plan              */
+  int32_t threads;        /* threads per workgroup of the MP kernel         */
 } mp_stats;
 
 /* Creates a plan for `batch` signals of lengths L[0..batch-1] and the W

@@ -836,6 +836,8 @@ int mp_get_kernel(const mp_plan* p, int32_t w, int32_t v, double* re, double* im
 int mp_get_stats(const mp_plan* p, mp_stats* out) {
   if (!p || !out) return MP_E_ARG;
   memset(out, 0, sizeof(*out));
+  out->group_leaves = p->G;
+  out->threads = p->nt;
   if (!p->analyzed) return MP_OK;
   if (hipStreamSynchronize(p->last_stream) != hipSuccess) return MP_E_HIP;
   std::vector<SigState> st((size_t)p->batch);
