@@ -158,7 +158,7 @@ def main():
     # ---- accuracy of the sampled signals against the oracle ----
     acc = None
     if orc:
-        agree, gap_first, dE = [], [], []
+        agree, gap_first, floor_first, dE = [], [], [], []
         for i, r in orc.items():
             ga = plan.atoms(i)
             n = min(len(ga), r["n_atoms"])
@@ -166,13 +166,21 @@ def main():
             fm = n if same.all() else int(np.argmin(same))
             small = np.nonzero(r["gap"] < 1e-6)[0]
             kg = int(small[0]) if len(small) else r["n_atoms"]
+            # FP32 floor: relative rounding error of |rho|^2 grows like
+            # 1e-6 sqrt(E0 / E_k) as the residual decays
+            E_before = np.concatenate([[r["E0"]], r["E"][:-1]])
+            floor = np.maximum(1e-6, 1e-6 * np.sqrt(r["E0"] / np.maximum(E_before, 1e-300)))
+            small_f = np.nonzero(r["gap"] < floor)[0]
+            kf = int(small_f[0]) if len(small_f) else r["n_atoms"]
             agree.append(fm)
             gap_first.append(kg)
+            floor_first.append(kf)
             if fm:
                 dE.append(float(np.max(np.abs(ga["E_after"][:fm] - r["E"][:fm])) / r["E0"]))
         acc = dict(signals=list(orc.keys()), agree_len=agree, first_gap_below_1e6=gap_first,
+                   first_gap_below_fp32_floor=floor_first,
                    ok=all(a >= g or a == min(len(plan.atoms(i)), orc[i]["n_atoms"])
-                          for a, g, i in zip(agree, gap_first, orc.keys())),
+                          for a, g, i in zip(agree, floor_first, orc.keys())),
                    max_dE_over_E0=max(dE) if dE else None)
 
     # ---- plain single-signal FP64 GPU path on a sample ----

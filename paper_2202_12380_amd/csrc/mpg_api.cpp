@@ -267,6 +267,9 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
   if (rc) return rc;
   for (int s = 0; s < batch; ++s)
     if (L[s] <= 0) return MP_E_ARG;
+  // the DGT keeps one frame's half-length FFT in LDS
+  for (int w = 0; w < W; ++w)
+    if ((size_t)(dicts[w].M / 2) * ((flags & MP_PREC_F64) ? 16 : 8) > 160 * 1024) return MP_E_LIMIT;
   {
     // padded lengths must fit every pair's kernel (checked before any HIP call)
     int64_t q = 1, need = 0;

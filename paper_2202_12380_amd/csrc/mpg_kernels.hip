@@ -395,10 +395,14 @@ __global__ void __launch_bounds__(256) k_energy(const XT* __restrict__ x, const 
 // --------------------------------------------------------------------------
 // DGT analysis (Sec. 5): for frame n of system w,
 //   rho(m, n) = sum_{t=-gl/2}^{gl/2-1} x(n a + t) g(t) exp(-2 pi i m t / M),
-// the length-M DFT of the windowed frame laid out circularly (t mod M).
-// One workgroup per frame: bit-reversed load into LDS, radix-2 DIT stages,
-// bins 0..M/2 written contiguously (m fastest).  The signal is zero beyond L
-// and circular over L_padded.
+// the length-M DFT of the windowed frame u laid out circularly (t mod M).
+// u is real, so one complex FFT of length H = M/2 suffices: with
+// z(q) = u(2q) + i u(2q+1) and Z = FFT_H(z),
+//   rho(m) = (Z(m) + conj Z(H-m)) / 2 + e^{-2 pi i m / M} (Z(m) - conj Z(H-m)) / (2i),
+// indices of Z mod H, m = 0..M/2.  One workgroup per frame: bit-reversed load
+// into LDS (H complex entries), radix-2 DIT stages, then the unpacking fused
+// with the plane write and the max-tree leaves (16 bins per leaf).  The signal
+// is zero beyond L and circular over L_padded.
 
 template <typename R, typename XT>
 __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const SigDev* __restrict__ sigs,
@@ -408,6 +412,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
                                              Cx<R>* __restrict__ planes, Leaf<R>* __restrict__ leaves) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem_raw);
+  const int H = M >> 1, logH = logM - 1;
   const int64_t f = blockIdx.x;
   // signal owning global frame f: last s with frame_prefix[s] <= f
   int lo = 0, hi = batch - 1;
@@ -421,23 +426,29 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
   const int64_t n = f - frame_prefix[s];
   const int64_t L = S.L, Lp = S.Lp;
   const XT* xs = x + S.x_off;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const int t = i < M / 2 ? i : i - M;
-    R v = (R)0;
-    if (t >= -gl / 2 && t < gl / 2) {
-      int64_t l = (n * a + t) % Lp;
-      if (l < 0) l += Lp;
-      if (l < L) v = (R)xs[l] * win[t + gl / 2];
+  for (int q = threadIdx.x; q < H; q += blockDim.x) {
+    R v2[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = 2 * q + e;
+      const int t = i < H ? i : i - M;
+      R v = (R)0;
+      if (t >= -gl / 2 && t < gl / 2) {
+        int64_t l = (n * a + t) % Lp;
+        if (l < 0) l += Lp;
+        if (l < L) v = (R)xs[l] * win[t + gl / 2];
+      }
+      v2[e] = v;
     }
-    const int r = (int)(__brev((unsigned)i) >> (32 - logM));
-    buf[r].re = v;
-    buf[r].im = (R)0;
+    const int r = logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0;
+    buf[r].re = v2[0];
+    buf[r].im = v2[1];
   }
   __syncthreads();
-  for (int ls = 1; ls <= logM; ++ls) {
+  for (int ls = 1; ls <= logH; ++ls) {
     const int half = 1 << (ls - 1);
-    const int tstride = M >> ls;  // twiddle index step
-    for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
+    const int tstride = 2 * (H >> ls);  // e^{-2 pi i pos / 2^ls} = tw[pos * M / 2^ls]
+    for (int b = threadIdx.x; b < H / 2; b += blockDim.x) {
       const int grp = b >> (ls - 1);
       const int pos = b & (half - 1);
       const int i0 = (grp << ls) + pos, i1 = i0 + half;
@@ -451,10 +462,9 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
     }
     __syncthreads();
   }
+  // unpack, write the plane row and the leaves: leaf i = maximum of |rho|^2
+  // over bins 16 i .. 16 i + 15 (ties to the lowest bin), one DPP row per leaf
   Cx<R>* out = planes + S.coef_base + S.off[w] + n * MR;
-  for (int m = threadIdx.x; m < MR; m += blockDim.x) out[m] = buf[m];
-  // max-tree leaves of this frame (Sec. 5.1): leaf i = maximum of |rho|^2 over
-  // bins 16 i .. 16 i + 15 (ties to the lowest bin), one DPP row per leaf
   const int lpf = (MR + ROW - 1) >> LOG_ROW;
   Leaf<R>* lf = leaves + S.leaf_base + S.lbase[w] + n * lpf;
   const uint32_t p0 = (uint32_t)(S.off[w] + n * MR);
@@ -463,7 +473,17 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
     const int m = m0 + threadIdx.x;
     const bool valid = m < MR;
     Cx<R> v = {(R)0, (R)0};
-    if (valid) v = buf[m];
+    if (valid) {
+      const Cx<R> zk = buf[m & (H - 1)], zr = buf[(H - m) & (H - 1)];
+      // even part (zk + conj zr) / 2, odd part (zk - conj zr) / (2i)
+      const R er = (R)0.5 * (zk.re + zr.re), ei = (R)0.5 * (zk.im - zr.im);
+      const R or_ = (R)0.5 * (zk.im + zr.im), oi = (R)0.5 * (zr.re - zk.re);
+      Cx<R> t = {(R)-1, (R)0};
+      if (m < H) t = tw[m];
+      v.re = er + (t.re * or_ - t.im * oi);
+      v.im = ei + (t.re * oi + t.im * or_);
+      out[m] = v;
+    }
     const R val = v.re * v.re + v.im * v.im;
     const uint64_t bits = valid ? val_bits(val) : 0ull;
     const uint64_t rm = row_max_bits<R>(bits);
@@ -1647,8 +1667,12 @@ hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, in
   if (frames <= 0) return hipSuccess;
   int logM = 0;
   while ((1 << logM) < M) ++logM;
-  const size_t sh = (size_t)M * (f64 ? 16 : 8);
+  const size_t sh = (size_t)(M / 2) * (f64 ? 16 : 8);
+  if (sh > 160 * 1024) return hipErrorInvalidValue;
   const dim3 grid((unsigned)frames);
+  const void* kf = f64 ? (dtype == 0 ? (const void*)k_dgt<double, float> : (const void*)k_dgt<double, double>)
+                       : (dtype == 0 ? (const void*)k_dgt<float, float> : (const void*)k_dgt<float, double>);
+  if (sh > 64 * 1024) CHK(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
   if (f64) {
     if (dtype == 0)
       k_dgt<double, float><<<grid, 256, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
