@@ -56,6 +56,12 @@ extern "C" {
 #define MP_PREC_F64 0x1u         /* FP64 planes, kernels and updates               */
 #define MP_THR_REL 0x10u         /* threshold relative to each kernel's peak |h|   */
 #define MP_CONJ_GATE_GAMMA 0x20u /* conjugate-partner update only when gamma != 0  */
+/* DFT inside the analysis (FP32 plans only; default: FP32 radix-2 FFT).  The
+ * split variants run the DFT on matrix cores as a four-step transform with
+ * each operand a pair of half-precision numbers (hi + lo; products
+ * hi*hi + hi*lo + lo*hi accumulated in FP32); systems need M <= 16384. */
+#define MP_DFT_F16SPLIT 0x40u    /* FP16 pairs                                      */
+#define MP_DFT_BF16SPLIT 0x80u   /* BF16 pairs                                      */
 
 /* ---- input sample types for mp_analyze / output types for mp_resynth ---- */
 #define MP_DTYPE_F32 0
@@ -123,8 +129,11 @@ typedef struct {
  * FP64, every truncated cross-kernel h_{w,v} on its common grid (Sec. 4.1,
  * 4.2; threshold Eq. truncgram, absolute unless MP_THR_REL) plus FP32 copies.
  * kernel_tol is the threshold epsilon (> 0).  flags: MP_PREC_*, MP_THR_REL,
- * MP_CONJ_GATE_GAMMA.  Uses the current HIP device; blocks until the
- * kernels are built.  *out receives the plan. */
+ * MP_CONJ_GATE_GAMMA, at most one MP_DFT_* (not with MP_PREC_F64).  Uses the
+ * current HIP device; blocks until the kernels are built.  *out receives the
+ * plan.  MP_E_LIMIT: a frame's FFT exceeds the LDS of one workgroup (M/2
+ * complex entries; twice that for MP_DFT_*), or the signal's tree groups do
+ * not fit it. */
 int mp_plan_create(const mp_dict *dicts, int32_t W, const int64_t *L,
                    int32_t batch, double kernel_tol, uint32_t flags,
                    mp_plan **out);

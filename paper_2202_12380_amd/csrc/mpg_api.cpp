@@ -24,6 +24,11 @@ hipError_t launch_gram_extract(const double2* t, int D, int Mmax, double thr, in
                                int width, double2* o64, float2* o32, hipStream_t st);
 hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch, SigState* st_,
                          hipStream_t st);
+hipError_t launch_dft_tables(int fmt, int N, int Np, uint16_t* out, hipStream_t st);
+hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a, int M,
+                           int MR, const int64_t* frame_prefix, int batch, int64_t frames, const float* win,
+                           const void* tw, int N1, int N2, const uint16_t* F1, const uint16_t* F2, void* planes,
+                           void* leaves, hipStream_t st);
 hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
                       const void* win, const void* tw, void* planes, void* leaves, hipStream_t st);
@@ -45,6 +50,9 @@ struct mp_plan {
   uint32_t flags = 0;
   double eps = 0.0;
   bool f64 = false;
+  int dft_fmt = -1;  // -1: FP32/FP64 FFT, 0: FP16 pairs on MFMA, 1: BF16 pairs
+  std::vector<int> dft_n1, dft_n2;
+  std::vector<uint16_t*> d_dft1, d_dft2;
   std::vector<mp_dict> dicts;
   std::vector<DictDev> hd;
   std::vector<PairDev> hp;
@@ -156,6 +164,8 @@ void free_plan(mp_plan* p) {
   hipFree(p->d_queue);
   for (auto& f : p->d_fprefix) hipFree(f);
   hipFree(p->d_acc);
+  for (auto t : p->d_dft1) hipFree(t);
+  for (auto t : p->d_dft2) hipFree(t);
   if (p->ev_valid)
     for (auto& e : p->ev) hipEventDestroy(e);
   delete p;
@@ -262,14 +272,18 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
   *out = nullptr;
   if (!dicts || !L || W < 1 || W > MAXW || batch < 1 || batch > (1 << 20)) return MP_E_ARG;
   if (!(kernel_tol >= 0.0 && kernel_tol < 1.0)) return MP_E_ARG;
-  if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA)) return MP_E_ARG;
+  if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA | MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT))
+    return MP_E_ARG;
+  const uint32_t dftf = flags & (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT);
+  if (dftf == (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT) || (dftf && (flags & MP_PREC_F64))) return MP_E_ARG;
   int rc = check_dicts(dicts, W);
   if (rc) return rc;
   for (int s = 0; s < batch; ++s)
     if (L[s] <= 0) return MP_E_ARG;
   // the DGT keeps one frame's half-length FFT in LDS
   for (int w = 0; w < W; ++w)
-    if ((size_t)(dicts[w].M / 2) * ((flags & MP_PREC_F64) ? 16 : 8) > 160 * 1024) return MP_E_LIMIT;
+    if ((size_t)(dicts[w].M / 2) * ((flags & MP_PREC_F64) ? 16 : 8) * (dftf ? 2 : 1) > 160 * 1024)
+      return MP_E_LIMIT;
   {
     // padded lengths must fit every pair's kernel (checked before any HIP call)
     int64_t q = 1, need = 0;
@@ -292,6 +306,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
   p->flags = flags;
   p->eps = kernel_tol;
   p->f64 = (flags & MP_PREC_F64) != 0;
+  p->dft_fmt = (flags & MP_DFT_F16SPLIT) ? 0 : ((flags & MP_DFT_BF16SPLIT) ? 1 : -1);
   p->dicts.assign(dicts, dicts + W);
   hipStream_t st = nullptr;
   double2* d_roots = nullptr;
@@ -465,6 +480,27 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       for (int w = 0; w < W; ++w)
         HCHK(launch_roots(p->hd[w].M, p->hd[w].M, +1, p->d_root64 + p->hd[w].root_off,
                           p->d_root32 + p->hd[w].root_off, st));
+    }
+
+    // ---- split half-precision DFT matrices for the four-step DFT ----
+    if (p->dft_fmt >= 0) {
+      p->dft_n1.assign(W, 0);
+      p->dft_n2.assign(W, 0);
+      p->d_dft1.assign(W, nullptr);
+      p->d_dft2.assign(W, nullptr);
+      for (int w = 0; w < W; ++w) {
+        const int H = dicts[w].M / 2;
+        int lh = 0;
+        while ((1 << lh) < H) ++lh;
+        const int n1 = 1 << ((lh + 1) / 2), n2 = H / n1;
+        p->dft_n1[w] = n1;
+        p->dft_n2[w] = n2;
+        const int n1p = std::max(n1, 16), n2p = std::max(n2, 16);
+        ACHK(dalloc(&p->d_dft1[w], (size_t)6 * n1p * n1p));
+        ACHK(dalloc(&p->d_dft2[w], (size_t)6 * n2p * n2p));
+        HCHK(launch_dft_tables(p->dft_fmt, n1, n1p, p->d_dft1[w], st));
+        HCHK(launch_dft_tables(p->dft_fmt, n2, n2p, p->d_dft2[w], st));
+      }
     }
 
     // ---- truncated cross-kernels, FP64 on the device (Sec. 4.1, 4.2) ----
@@ -681,9 +717,14 @@ int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream)
   for (int w = 0; w < p->W; ++w) {
     const DictDev& D = p->hd[w];
     const void* tw = p->f64 ? (const void*)(p->d_tw64 + D.tw_off) : (const void*)(p->d_tw32 + D.tw_off);
-    HCHK(launch_dgt(p->f64, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w], p->batch,
-                    p->frames_total[w], (const char*)win + D.win_off * (p->f64 ? 8 : 4), tw, p->d_planes,
-                    p->d_leaves, stream));
+    if (p->dft_fmt >= 0)
+      HCHK(launch_dgt_mfma(p->dft_fmt, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w],
+                           p->batch, p->frames_total[w], p->d_win32 + D.win_off, tw, p->dft_n1[w],
+                           p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves, stream));
+    else
+      HCHK(launch_dgt(p->f64, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w], p->batch,
+                      p->frames_total[w], (const char*)win + D.win_off * (p->f64 ? 8 : 4), tw, p->d_planes,
+                      p->d_leaves, stream));
   }
   HCHK(hipEventRecord(p->ev[1], stream));
   HCHK(hipEventRecord(p->ev[2], stream));

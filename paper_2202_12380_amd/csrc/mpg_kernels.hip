@@ -495,6 +495,294 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
 }
 
 // --------------------------------------------------------------------------
+// DGT with the DFT on matrix cores, in split half precision (FP16 or BF16
+// pairs hi + lo, products hi*hi + hi*lo + lo*hi, FP32 accumulation).  Same
+// result as k_dgt up to the split rounding.  The length-H complex FFT of the
+// real-input packing is done as a four-step DFT, H = N1 N2, n = n1 + N1 n2,
+// k = N2 k1 + k2:
+//   B(n1, k2) = sum_n2 z(n1 + N1 n2) w_N2^{n2 k2}   (GEMM, 16x16x16 MFMA tiles)
+//   B(n1, k2) *= w_H^{n1 k2}                           (FP32)
+//   Z(N2 k1 + k2) = sum_n1 w_N1^{k1 n1} B(n1, k2)       (GEMM)
+// with w_N = exp(-2 pi i / N).  The DFT matrices come split and already laid
+// out per MFMA operand (k_dft_tables); N1, N2 <= 128, padded with zeros to
+// multiples of 16.  The frame is scaled by a power of two to max |z| <= 1
+// before the split, so FP16 neither overflows nor loses the low part.
+
+typedef short mf_s4 __attribute__((ext_vector_type(4)));
+typedef _Float16 mf_h4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+template <int FMT>  // 0: FP16, 1: BF16
+__device__ __forceinline__ uint16_t to_half_bits(float x) {
+  if (FMT == 0) return __builtin_bit_cast(uint16_t, (_Float16)x);
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite x)
+  return (uint16_t)(u >> 16);
+}
+template <int FMT>
+__device__ __forceinline__ float from_half_bits(uint16_t b) {
+  if (FMT == 0) return (float)__builtin_bit_cast(_Float16, b);
+  return __uint_as_float((uint32_t)b << 16);
+}
+// x = hi + lo in the half format
+template <int FMT>
+__device__ __forceinline__ void split_half(float x, uint16_t& hi, uint16_t& lo) {
+  hi = to_half_bits<FMT>(x);
+  lo = to_half_bits<FMT>(x - from_half_bits<FMT>(hi));
+}
+template <int FMT>
+__device__ __forceinline__ mf_f4 mfma16(mf_s4 a, mf_s4 b, mf_f4 c) {
+  if constexpr (FMT == 0)
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(mf_h4, a), __builtin_bit_cast(mf_h4, b), c, 0,
+                                                0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+// c += (ah + al)(bh + bl) without al*bl
+template <int FMT>
+__device__ __forceinline__ mf_f4 mfma_split(mf_s4 ah, mf_s4 al, mf_s4 bh, mf_s4 bl, mf_f4 c) {
+  c = mfma16<FMT>(ah, bh, c);
+  c = mfma16<FMT>(ah, bl, c);
+  return mfma16<FMT>(al, bh, c);
+}
+
+// Operand tile (a, b) of the DFT matrix F(r, c) = w_N^{r c} (zero outside N):
+// lane l holds F(16 a + 4 (l >> 4) + j, 16 b + (l & 15)), j = 0..3; components
+// re_hi, re_lo, im_hi, im_lo, -im_hi, -im_lo, each T*T*256 halves (T = Np/16).
+// F is symmetric, so the same tile serves as the B operand of the first GEMM
+// (rows n2, columns k2) and, with (a, b) swapped, as the A operand of the
+// second (rows k1, columns n1).
+template <int FMT>
+__global__ void k_dft_tables(int N, int Np, uint16_t* __restrict__ out) {
+  const int a = blockIdx.y * blockDim.y + threadIdx.y, b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= Np || b >= Np) return;
+  double re = 0.0, im = 0.0;
+  if (a < N && b < N) {
+    const int64_t q = ((int64_t)a * b) % N;
+    sincospi(-2.0 * (double)q / (double)N, &im, &re);
+  }
+  const int T = Np >> 4;
+  const int A = a >> 4, qa = a & 15, B = b >> 4;
+  const int l = ((qa >> 2) << 4) | (b & 15), j = qa & 3;
+  const size_t idx = (((size_t)A * T + B) * 64 + l) * 4 + j;
+  const size_t plane = (size_t)Np * Np;
+  uint16_t h, lo;
+  split_half<FMT>((float)re, h, lo);
+  out[0 * plane + idx] = h;
+  out[1 * plane + idx] = lo;
+  split_half<FMT>((float)im, h, lo);
+  out[2 * plane + idx] = h;
+  out[3 * plane + idx] = lo;
+  split_half<FMT>((float)-im, h, lo);
+  out[4 * plane + idx] = h;
+  out[5 * plane + idx] = lo;
+}
+
+struct TileOp {
+  mf_s4 rh, rl, ih, il, nh, nl;  // re, im, -im (hi, lo)
+};
+__device__ __forceinline__ TileOp load_tile(const uint16_t* __restrict__ tab, int Np, int a, int b, int lane) {
+  const int T = Np >> 4;
+  const size_t plane = (size_t)Np * Np;
+  const size_t idx = (((size_t)a * T + b) * 64 + lane) * 4;
+  TileOp t;
+  t.rh = *reinterpret_cast<const mf_s4*>(tab + 0 * plane + idx);
+  t.rl = *reinterpret_cast<const mf_s4*>(tab + 1 * plane + idx);
+  t.ih = *reinterpret_cast<const mf_s4*>(tab + 2 * plane + idx);
+  t.il = *reinterpret_cast<const mf_s4*>(tab + 3 * plane + idx);
+  t.nh = *reinterpret_cast<const mf_s4*>(tab + 4 * plane + idx);
+  t.nl = *reinterpret_cast<const mf_s4*>(tab + 5 * plane + idx);
+  return t;
+}
+
+template <int FMT, typename XT>
+__global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, const SigDev* __restrict__ sigs, int w,
+                                                  int gl, int a, int M, int MR,
+                                                  const int64_t* __restrict__ frame_prefix, int batch,
+                                                  const float* __restrict__ win, const Cx<float>* __restrict__ tw,
+                                                  int N1, int N2, const uint16_t* __restrict__ F1,
+                                                  const uint16_t* __restrict__ F2, Cx<float>* __restrict__ planes,
+                                                  Leaf<float>* __restrict__ leaves) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int H = M >> 1;
+  Cx<float>* buf = reinterpret_cast<Cx<float>*>(smem_raw);  // z, then B
+  Cx<float>* ybuf = buf + H;                                  // Z
+  __shared__ float s_red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int N1p = N1 < 16 ? 16 : N1, N2p = N2 < 16 ? 16 : N2;
+  const int64_t f = blockIdx.x;
+  int lo = 0, hi = batch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (frame_prefix[mid] <= f) lo = mid;
+    else hi = mid - 1;
+  }
+  const int s = lo;
+  const SigDev& S = sigs[s];
+  const int64_t n = f - frame_prefix[s];
+  const int64_t L = S.L, Lp = S.Lp;
+  const XT* xs = x + S.x_off;
+  float amax = 0.0f;
+  for (int q = threadIdx.x; q < H; q += blockDim.x) {
+    float v2[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = 2 * q + e;
+      const int t = i < H ? i : i - M;
+      float v = 0.0f;
+      if (t >= -gl / 2 && t < gl / 2) {
+        int64_t l = (n * a + t) % Lp;
+        if (l < 0) l += Lp;
+        if (l < L) v = (float)xs[l] * win[t + gl / 2];
+      }
+      v2[e] = v;
+    }
+    buf[q].re = v2[0];
+    buf[q].im = v2[1];
+    amax = fmaxf(amax, fmaxf(fabsf(v2[0]), fabsf(v2[1])));
+  }
+  // block maximum -> power-of-two scale with max |z| * scale <= 1
+  for (int o = 32; o; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
+  if (lane == 0) s_red[wave] = amax;
+  __syncthreads();
+  amax = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+  int ex = 0;
+  if (amax > 0.0f) frexpf(amax, &ex);
+  const float scale = ldexpf(1.0f, -ex), unscale = ldexpf(1.0f, ex);
+
+  // ---- step 1: B = X F_N2 (row blocks of 16 n1), twiddle, in place ----
+  const int r16 = lane & 15, k4 = (lane >> 4) * 4;
+  for (int rb = wave; rb < (N1p >> 4); rb += 4) {
+    const int n1a = 16 * rb + r16;  // A-operand row of this lane
+    mf_s4 xr_h[8], xr_l[8], xi_h[8], xi_l[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      if (ks < (N2p >> 4)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n2 = 16 * ks + k4 + j;
+          Cx<float> v = {0.0f, 0.0f};
+          if (n1a < N1 && n2 < N2) v = buf[n1a + N1 * n2];
+          uint16_t h0, l0, h1, l1;
+          split_half<FMT>(v.re * scale, h0, l0);
+          split_half<FMT>(v.im * scale, h1, l1);
+          xr_h[ks][j] = (short)h0;
+          xr_l[ks][j] = (short)l0;
+          xi_h[ks][j] = (short)h1;
+          xi_l[ks][j] = (short)l1;
+        }
+      }
+    }
+    for (int ct = 0; ct < (N2p >> 4); ++ct) {
+      mf_f4 cr = {0.0f, 0.0f, 0.0f, 0.0f}, ci = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        if (ks < (N2p >> 4)) {
+          const TileOp F = load_tile(F2, N2p, ks, ct, lane);
+          // (xr + i xi)(fr + i fi): re = xr fr + xi (-fi), im = xr fi + xi fr
+          cr = mfma_split<FMT>(xr_h[ks], xr_l[ks], F.rh, F.rl, cr);
+          cr = mfma_split<FMT>(xi_h[ks], xi_l[ks], F.nh, F.nl, cr);
+          ci = mfma_split<FMT>(xr_h[ks], xr_l[ks], F.ih, F.il, ci);
+          ci = mfma_split<FMT>(xi_h[ks], xi_l[ks], F.rh, F.rl, ci);
+        }
+      }
+      // lane holds rows n1 = 16 rb + k4 + j of column k2 = 16 ct + r16
+      const int k2 = 16 * ct + r16;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n1 = 16 * rb + k4 + j;
+        if (n1 < N1 && k2 < N2) {
+          const int jj = 2 * ((n1 * k2) & (H - 1));  // w_H^{n1 k2} = e^{-2 pi i jj / M}
+          Cx<float> t = tw[jj < H ? jj : jj - H];
+          if (jj >= H) {
+            t.re = -t.re;
+            t.im = -t.im;
+          }
+          Cx<float> o;
+          o.re = cr[j] * t.re - ci[j] * t.im;
+          o.im = cr[j] * t.im + ci[j] * t.re;
+          buf[n1 + N1 * k2] = o;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- step 2: Z = F_N1 B (column blocks of 16 k2) ----
+  for (int ct = wave; ct < (N2p >> 4); ct += 4) {
+    const int k2b = 16 * ct + r16;  // B-operand column of this lane
+    mf_s4 br_h[8], br_l[8], bi_h[8], bi_l[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      if (ks < (N1p >> 4)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n1 = 16 * ks + k4 + j;
+          Cx<float> v = {0.0f, 0.0f};
+          if (n1 < N1 && k2b < N2) v = buf[n1 + N1 * k2b];
+          uint16_t h0, l0, h1, l1;
+          split_half<FMT>(v.re, h0, l0);
+          split_half<FMT>(v.im, h1, l1);
+          br_h[ks][j] = (short)h0;
+          br_l[ks][j] = (short)l0;
+          bi_h[ks][j] = (short)h1;
+          bi_l[ks][j] = (short)l1;
+        }
+      }
+    }
+    for (int rt = 0; rt < (N1p >> 4); ++rt) {
+      mf_f4 cr = {0.0f, 0.0f, 0.0f, 0.0f}, ci = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        if (ks < (N1p >> 4)) {
+          const TileOp F = load_tile(F1, N1p, ks, rt, lane);  // F(k1, n1) tile (rt, ks), F symmetric
+          // (fr + i fi)(br + i bi): re = fr br + (-fi) bi, im = fr bi + fi br
+          cr = mfma_split<FMT>(F.rh, F.rl, br_h[ks], br_l[ks], cr);
+          cr = mfma_split<FMT>(F.nh, F.nl, bi_h[ks], bi_l[ks], cr);
+          ci = mfma_split<FMT>(F.rh, F.rl, bi_h[ks], bi_l[ks], ci);
+          ci = mfma_split<FMT>(F.ih, F.il, br_h[ks], br_l[ks], ci);
+        }
+      }
+      const int k2 = 16 * ct + r16;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k1 = 16 * rt + k4 + j;
+        if (k1 < N1 && k2 < N2) ybuf[N2 * k1 + k2] = Cx<float>{cr[j] * unscale, ci[j] * unscale};
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- unpack the real-input packing, plane row, leaves ----
+  Cx<float>* out = planes + S.coef_base + S.off[w] + n * MR;
+  const int lpf = (MR + ROW - 1) >> LOG_ROW;
+  Leaf<float>* lf = leaves + S.leaf_base + S.lbase[w] + n * lpf;
+  const uint32_t p0 = (uint32_t)(S.off[w] + n * MR);
+  for (int m0 = 0; m0 < lpf * ROW; m0 += blockDim.x) {
+    const int m = m0 + threadIdx.x;
+    const bool valid = m < MR;
+    Cx<float> v = {0.0f, 0.0f};
+    if (valid) {
+      const Cx<float> zk = ybuf[m & (H - 1)], zr = ybuf[(H - m) & (H - 1)];
+      const float er = 0.5f * (zk.re + zr.re), ei = 0.5f * (zk.im - zr.im);
+      const float or_ = 0.5f * (zk.im + zr.im), oi = 0.5f * (zr.re - zk.re);
+      Cx<float> t = {-1.0f, 0.0f};
+      if (m < H) t = tw[m];
+      v.re = er + (t.re * or_ - t.im * oi);
+      v.im = ei + (t.re * oi + t.im * or_);
+      out[m] = v;
+    }
+    const float val = v.re * v.re + v.im * v.im;
+    const uint64_t bits = valid ? val_bits(val) : 0ull;
+    const uint64_t rm = row_max_bits<float>(bits);
+    const uint64_t bal = __ballot(valid && bits == rm);
+    const uint32_t rowbits = (uint32_t)(bal >> (lane & ~(ROW - 1))) & 0xFFFFu;
+    if (rowbits && lane == (lane & ~(ROW - 1)) + __ffs(rowbits) - 1)
+      lf[m >> LOG_ROW] = make_leaf(KeyOps<float>::make(val, p0 + (uint32_t)m), v.re, v.im);
+  }
+}
+
+// --------------------------------------------------------------------------
 // The MP loop (Alg. 1 with Eq. approxResDef, the real-atom pairs of Sec. 5
 // and the residual update of Alg. 3).  One persistent workgroup per signal;
 // signals come from a queue, longest first.
@@ -1692,6 +1980,45 @@ hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, in
                                                   batch, (const float*)win, (const Cx<float>*)tw,
                                                   (Cx<float>*)planes, (Leaf<float>*)leaves);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_tables(int fmt, int N, int Np, uint16_t* out, hipStream_t st) {
+  const dim3 blk(16, 16), grid((unsigned)(Np / 16), (unsigned)(Np / 16));
+  if (fmt == 0)
+    k_dft_tables<0><<<grid, blk, 0, st>>>(N, Np, out);
+  else
+    k_dft_tables<1><<<grid, blk, 0, st>>>(N, Np, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a, int M,
+                           int MR, const int64_t* frame_prefix, int batch, int64_t frames, const float* win,
+                           const void* tw, int N1, int N2, const uint16_t* F1, const uint16_t* F2, void* planes,
+                           void* leaves, hipStream_t st) {
+  if (frames <= 0) return hipSuccess;
+  const size_t sh = (size_t)M * 8;  // z / B and Z, H complex FP32 each
+  if (sh > 160 * 1024) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)frames);
+  const Cx<float>* twc = (const Cx<float>*)tw;
+  Cx<float>* pl = (Cx<float>*)planes;
+  Leaf<float>* lv = (Leaf<float>*)leaves;
+#define DGT_MFMA(F, XT)                                                                                     \
+  do {                                                                                                      \
+    if (sh > 64 * 1024)                                                                                     \
+      CHK(hipFuncSetAttribute((const void*)k_dgt_mfma<F, XT>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+                              (int)sh));                                                                    \
+    k_dgt_mfma<F, XT><<<grid, 256, sh, st>>>((const XT*)x, sigs, w, gl, a, M, MR, frame_prefix, batch, win,  \
+                                             twc, N1, N2, F1, F2, pl, lv);                                  \
+  } while (0)
+  if (fmt == 0) {
+    if (dtype == 0) DGT_MFMA(0, float);
+    else DGT_MFMA(0, double);
+  } else {
+    if (dtype == 0) DGT_MFMA(1, float);
+    else DGT_MFMA(1, double);
+  }
+#undef DGT_MFMA
   return hipGetLastError();
 }
 

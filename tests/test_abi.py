@@ -46,6 +46,9 @@ def test_strerror_and_argument_errors_without_gpu():
         ([(5, 64, 16, 64)], [1024], 1e-4, 0, mpg.MP_E_ARG),                     # window
         ([(0, 64, 16, 64)], [1024], 1e-4, 0x100, mpg.MP_E_ARG),                 # flags
         ([(0, 32768, 8192, 32768)], [65536], 1e-4, 1, mpg.MP_E_LIMIT),          # FP64 frame FFT exceeds LDS
+        ([(0, 32768, 8192, 32768)], [65536], 1e-4, 0x40, mpg.MP_E_LIMIT),       # split DFT frame exceeds LDS
+        ([(0, 64, 16, 64)], [1024], 1e-4, 0x41, mpg.MP_E_ARG),                  # split DFT with FP64
+        ([(0, 64, 16, 64)], [1024], 1e-4, 0xC0, mpg.MP_E_ARG),                  # two DFT formats
     ]
     for dicts, lens, eps, flags, code in cases:
         with pytest.raises(mpg.MPError) as e:

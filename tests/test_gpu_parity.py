@@ -84,6 +84,32 @@ def test_dgt_planes(prec, dicts, L):
     assert abs(inf.E0 - float(xs @ xs)) <= 1e-12 * float(xs @ xs)
 
 
+@pytest.mark.parametrize("fmt,tol", [(0x40, 3e-6), (0x80, 5e-5)])
+@pytest.mark.parametrize("dicts,L", [
+    ([(0, 512, 128, 512)], 16384),
+    ([(0, 64, 16, 64), (0, 256, 64, 256)], 3000),
+    ([(1, 32, 8, 32), (0, 128, 32, 128), (0, 128, 128, 512)], 1024),
+    ([(0, 16384, 4096, 16384), (0, 4096, 1024, 4096)], 1 << 16),
+    ([(0, 4, 2, 4), (0, 8, 2, 8)], 64),
+])
+def test_dgt_planes_split_mfma(fmt, tol, dicts, L):
+    # DFT on matrix cores with FP16 (0x40) or BF16 (0x80) hi/lo operand pairs;
+    # tolerance relative to the plane maximum: the pair carries 22 (FP16) or
+    # 16 (BF16) significant bits, two GEMM stages
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    x = np.random.default_rng(L + 1).standard_normal(L).astype(np.float32).astype(np.float64)
+    plan = mpg.Plan(dicts, [L], 1e-4, fmt)
+    plan.analyze(torch.from_numpy(x).to(torch.float32).cuda())
+    Lp = O.padded_length(dicts, L)
+    xp = np.zeros(Lp)
+    xp[:L] = x
+    for w, d in enumerate(dicts):
+        ref = O.dgt(d, xp)
+        got = plan.residual(0, w).cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max()
+
+
 # --------------------------------------------------------------------------
 # MP loop, FP64: identical atom sequence
 
@@ -124,6 +150,21 @@ def test_mp_fp32_c1():
     orc = oracle_run(wl.dicts, x, wl.eps, K=wl.K, x_dtype=np.float32)
     fm, kg = assert_tolerance(ga[0], orc)
     assert fm >= 100
+
+
+@pytest.mark.parametrize("fmt,gap_tol,e_tol", [(0x40, 1e-6, 1e-5), (0x80, 3e-5, 1e-4)])
+def test_mp_split_dft_batch(fmt, gap_tol, e_tol):
+    # FP32 loop on planes from the split half-precision DFT: FP16 pairs keep
+    # the FP32 agreement rule; BF16 pairs start from planes with ~1e-5
+    # relative error, so near-ties below 3e-5 may go either way
+    _torch()
+    dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)]
+    lens = [16384, 9000, 20000]
+    xs = [S.audio_like(L, S.rng(78, i)).astype(np.float32) for i, L in enumerate(lens)]
+    _, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=fmt)
+    for i, x in enumerate(xs):
+        orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32)
+        assert_tolerance(ga[i], orc, gap_tol=gap_tol, e_tol=e_tol)
 
 
 def test_mp_fp32_batch_ragged():
