@@ -77,9 +77,15 @@ def main():
     ap.add_argument("--fp64-sample", type=int, default=4, help="signals run on the plain FP64 GPU path")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--study", choices=["precision"], default=None,
+                    help="precision: analysis DFT in FP16 / BF16 pairs, FP32, FP64 at thresholds "
+                         "1e-3 / 1e-4 / 1e-5, agreement with the oracle on sampled signals")
     args = ap.parse_args()
     if args.calib_copy > 0:
         calib_copy(args.calib_copy)
+        return
+    if args.study == "precision":
+        precision_study(args)
         return
     if args.gpus != 1:
         sys.stderr.write("bench.py measures one GPU only: this build runs on a single MI355X and has "
@@ -238,6 +244,70 @@ def main():
         "counters": {"updated": int(st.updated), "blocks": int(st.blocks), "groups": int(st.l1_groups)},
     }
     print(json.dumps(out))
+
+
+def _agreement(ga, r):
+    """First selection where the GPU sequence leaves the oracle's, the first
+    top-2 gaps below 1e-6 and below the FP32 floor 1e-6 sqrt(E0 / E_k), and the
+    largest energy difference (relative to ||x||^2) before the divergence."""
+    n = min(len(ga), r["n_atoms"])
+    same = (ga["w"][:n] == r["w"][:n]) & (ga["m"][:n] == r["m"][:n]) & (ga["n"][:n] == r["n"][:n])
+    fm = n if same.all() else int(np.argmin(same))
+    E_before = np.concatenate([[r["E0"]], r["E"][:-1]])
+    floor = np.maximum(1e-6, 1e-6 * np.sqrt(r["E0"] / np.maximum(E_before, 1e-300)))
+    g6 = np.nonzero(r["gap"] < 1e-6)[0]
+    gf = np.nonzero(r["gap"] < floor)[0]
+    dE = float(np.max(np.abs(ga["E_after"][:fm] - r["E"][:fm])) / r["E0"]) if fm else 0.0
+    return dict(agree=fm, oracle_atoms=int(r["n_atoms"]), gpu_atoms=int(len(ga)),
+                first_gap_1e6=int(g6[0]) if len(g6) else int(r["n_atoms"]),
+                first_gap_floor=int(gf[0]) if len(gf) else int(r["n_atoms"]), max_dE_over_E0=dE)
+
+
+def precision_study(args):
+    """The batch with the analysis DFT in FP16 pairs and BF16 pairs (matrix
+    cores), FP32 and FP64 (FFT), at kernel thresholds 1e-3, 1e-4, 1e-5: DGT
+    time and rate, loop rate, and agreement with the oracle on four sampled
+    signals of different lengths (one JSON line per case)."""
+    import torch
+    from paper_2202_12380_amd import mpg
+    wl = S.workload(3)
+    lengths = wl.lengths[: args.batch]
+    xs = S.signals(3, batch=args.batch)
+    order = np.argsort(lengths)
+    sample = sorted({int(order[i * len(order) // 4]) for i in range(4)})
+    eps_list = (1e-3, 1e-4, 1e-5)
+    jobs = [(wl.dicts, xs[i].astype(np.float64), e, SNR_DB, K_CAP) for e in eps_list for i in sample]
+    log("oracle on signals %s at %d thresholds" % (sample, len(eps_list)))
+    ctx = mp_.get_context("fork")
+    with ctx.Pool(processes=min(len(jobs), 12)) as pool:
+        res = pool.map(_oracle_job, jobs, chunksize=1)
+    orc = {(e, i): res[k * len(sample) + j] for k, e in enumerate(eps_list) for j, i in enumerate(sample)}
+    dev = torch.device("cuda", 0)
+    x32 = torch.from_numpy(np.concatenate(xs).astype(np.float32)).to(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    formats = (("fp16 pairs (MFMA)", mpg.MP_DFT_F16SPLIT), ("bf16 pairs (MFMA)", mpg.MP_DFT_BF16SPLIT),
+               ("fp32 (FFT)", 0), ("fp64 (FFT, FP64 loop)", mpg.MP_PREC_F64))
+    for e in eps_list:
+        for name, flags in formats:
+            plan = mpg.Plan(wl.dicts, lengths, e, flags)
+            plan.analyze(x32, stream)
+            plan.run(K_CAP, SNR_DB, stream)
+            torch.cuda.synchronize()
+            plan.analyze(x32, stream)
+            plan.run(K_CAP, SNR_DB, stream)
+            torch.cuda.synchronize()
+            st = plan.stats()
+            infos = [plan.info(s) for s in range(len(lengths))]
+            coefs = sum(int(i.n_coefs) for i in infos)
+            dgt_bytes = 4.0 * sum(lengths) * len(wl.dicts) + 8.0 * coefs * (2 if flags & 1 else 1)
+            agree = {int(i): _agreement(plan.atoms(int(i)), orc[(e, int(i))]) for i in sample}
+            print(json.dumps({"study": "precision", "eps": e, "dft": name, "dgt_ms": st.dgt_ms,
+                              "dgt_GB_per_s": dgt_bytes / (st.dgt_ms * 1e-3) / 1e9,
+                              "loop_ms": st.loop_ms, "atoms": int(st.atoms),
+                              "atoms_per_s": st.atoms / (st.loop_ms * 1e-3),
+                              "min_snr_db": float(min(10 * np.log10(i.E0 / max(i.E, 1e-300)) for i in infos)),
+                              "sampled": agree}), flush=True)
+            plan.close()
 
 
 def calib_copy(nbytes):
