@@ -154,6 +154,24 @@ int mp_analyze(mp_plan *plan, const void *x_dev, int32_t dtype,
 int mp_run(mp_plan *plan, int64_t max_atoms, double target_snr_db,
            hipStream_t stream);
 
+/* Approximate MP with resets (Alg. 2), from a fresh mp_analyze of the same
+ * x_dev (same layout and dtype).  The inner loop (Alg. 1 on the current
+ * residual's coefficients) runs until reset_it selections (> 0) or, when
+ * reset_db < 0, until its error estimate falls below 10^(reset_db/10) times
+ * the error at the last reset, or until any stop rule of mp_run.  Then the
+ * selections are added to the solution, synthesized, and subtracted from the
+ * true residual r = x - D c (FP64, over the padded length); ||r||^2 becomes
+ * the error and rho = D* r the new coefficients.  A signal finishes when its
+ * true error reaches target_snr_db (> 0), when max_atoms selections were made
+ * (<= 0: L_padded/5), when all coefficients are zero, or when an inner loop
+ * made no selection.  The atom log holds every selection; E_after is the
+ * inner estimate, reset to the true error at each reset.  Synchronizes with
+ * the stream once per reset round.  MP_E_STATE unless called right after
+ * mp_analyze; MP_E_ARG for reset_it <= 0 or reset_db > 0. */
+int mp_run_resets(mp_plan *plan, const void *x_dev, int32_t dtype,
+                  int64_t max_atoms, double target_snr_db, int64_t reset_it,
+                  double reset_db, hipStream_t stream);
+
 /* Copies up to `cap` selected atoms of signal `sig` to out_host, in
  * selection order; *n_out receives the number of atoms selected. */
 int mp_get_atoms(const mp_plan *plan, int32_t sig, mp_atom *out_host,

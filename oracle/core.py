@@ -205,3 +205,82 @@ def resynth(dicts, Lp: int, w, m, n, c) -> np.ndarray:
     _check(lib().orc_resynth(_dicts(dicts), len(dicts), Lp, len(w), w, m, n,
                              np.ascontiguousarray(c.real), np.ascontiguousarray(c.imag), y))
     return y
+
+
+@dataclass
+class ResetResult:
+    w: np.ndarray
+    m: np.ndarray
+    n: np.ndarray
+    c: np.ndarray
+    E: np.ndarray        # inner error estimate after each selection (restarts at the true error)
+    gap: np.ndarray      # relative top-2 gap of |rho|^2 at each selection
+    E0: float
+    L_padded: int
+    stop_reason: int
+    E_true: np.ndarray   # true error ||x - D c||^2 after each reset round
+    k_rounds: np.ndarray  # selections made when each round ended
+    residual: np.ndarray  # final true residual over the padded length
+
+    @property
+    def n_atoms(self):
+        return len(self.w)
+
+
+def mp_resets(dicts, x: np.ndarray, eps: float, K: int = 0, target_db: float = 0.0,
+              reset_it: int = 1, reset_db: float = 0.0, flags: int = 0) -> ResetResult:
+    """Approximate coefficient-domain MP with resets (Alg. 2), composed of this
+    oracle's own steps.  Each inner loop is mp() (Alg. 1) started from the
+    coefficients of the current true residual, rho = D* r, with error E = ||r||^2;
+    it runs until reset_it selections, or (reset_db < 0) until its estimate
+    falls to 10^(reset_db/10) of the error at the last reset, or any stop rule
+    of Alg. 1.  The outer update adds the selections to the solution and
+    subtracts their synthesis (resynth()) from r; ||r||^2 becomes the error.
+    The procedure ends when the true error reaches target_db below ||x||^2,
+    after K selections (0: L_padded/5), when the coefficients vanish, or when
+    an inner loop selects nothing."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    L = len(x)
+    Lp = padded_length(dicts, L)
+    if Lp < 0:
+        raise RuntimeError("oracle error %d" % Lp)
+    r = np.zeros(Lp)
+    r[:L] = x
+    E0 = float(r @ r)
+    kmax = K if K > 0 else Lp // 5
+    Etg = E0 * 10.0 ** (-target_db / 10.0) if target_db > 0 else -np.inf
+    ws, ms, ns, cs, Es, gs, Et, kr = [], [], [], [], [], [], [], []
+    k, Eout, stop = 0, E0, 0
+    while True:
+        Ein = Etg
+        if reset_db < 0:
+            Ein = max(Ein, Eout * 10.0 ** (reset_db / 10.0))
+        t_db = 10.0 * np.log10(Eout / Ein) if 0 < Ein < Eout else 0.0
+        kin = min(reset_it, kmax - k)
+        res = mp(dicts, r, eps, K=kin, target_db=t_db, flags=flags, cap=kin)
+        ws.append(res.w)
+        ms.append(res.m)
+        ns.append(res.n)
+        cs.append(res.c)
+        Es.append(res.E)
+        gs.append(res.gap)
+        k += res.n_atoms
+        if res.n_atoms:
+            r = r - resynth(dicts, Lp, res.w, res.m, res.n, res.c)
+        Eout = float(r @ r)
+        Et.append(Eout)
+        kr.append(k)
+        if Eout <= Etg:
+            stop = 2
+        elif k >= kmax:
+            stop = 1
+        elif res.stop_reason == 4:
+            stop = 4
+        elif res.n_atoms == 0:
+            stop = res.stop_reason or 1
+        if stop:
+            break
+    cat = lambda v, t: np.concatenate(v).astype(t) if v else np.zeros(0, t)
+    return ResetResult(cat(ws, np.int32), cat(ms, np.int32), cat(ns, np.int32), cat(cs, np.complex128),
+                       cat(Es, np.float64), cat(gs, np.float64), E0, Lp, stop, np.array(Et),
+                       np.array(kr, np.int64), r)

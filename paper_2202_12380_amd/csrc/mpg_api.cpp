@@ -24,6 +24,11 @@ hipError_t launch_gram_extract(const double2* t, int D, int Mmax, double thr, in
                                int width, double2* o64, float2* o32, hipStream_t st);
 hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch, SigState* st_,
                          hipStream_t st);
+hipError_t launch_reset_init(const void* x, int dtype, const SigDev* sigs, int batch, int64_t max_Lp,
+                             const int64_t* roff, double* r, hipStream_t st);
+hipError_t launch_reset_update(const AtomRec* atoms, const SigDev* sigs, SigState* st_, const DictDev* dicts,
+                               const double* win64, const int64_t* roff, double* r, int batch, double snr_db,
+                               int64_t K_total, int* active, hipStream_t st);
 hipError_t launch_dft_tables(int fmt, int N, int Np, uint16_t* out, hipStream_t st);
 hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a, int M,
                            int MR, const int64_t* frame_prefix, int batch, int64_t frames, const float* win,
@@ -53,6 +58,12 @@ struct mp_plan {
   int dft_fmt = -1;  // -1: FP32/FP64 FFT, 0: FP16 pairs on MFMA, 1: BF16 pairs
   std::vector<int> dft_n1, dft_n2;
   std::vector<uint16_t*> d_dft1, d_dft2;
+  // reset procedure: FP64 residuals (stride L_padded), their offsets and a
+  // copy of the signal table that reads them over the padded length
+  double* d_res = nullptr;
+  int64_t* d_roff = nullptr;
+  SigDev* d_sigs_res = nullptr;
+  int* d_active = nullptr;
   std::vector<mp_dict> dicts;
   std::vector<DictDev> hd;
   std::vector<PairDev> hp;
@@ -164,6 +175,10 @@ void free_plan(mp_plan* p) {
   hipFree(p->d_queue);
   for (auto& f : p->d_fprefix) hipFree(f);
   hipFree(p->d_acc);
+  hipFree(p->d_res);
+  hipFree(p->d_roff);
+  hipFree(p->d_sigs_res);
+  hipFree(p->d_active);
   for (auto t : p->d_dft1) hipFree(t);
   for (auto t : p->d_dft2) hipFree(t);
   if (p->ev_valid)
@@ -736,11 +751,7 @@ fail:
   return rc;
 }
 
-int mp_run(mp_plan* p, int64_t max_atoms, double target_snr_db, hipStream_t stream) {
-  if (!p) return MP_E_ARG;
-  if (!p->analyzed) return MP_E_STATE;
-  int rc = ensure_cap(p, max_atoms, stream);
-  if (rc) return rc;
+static MPArgs mp_args(const mp_plan* p, int64_t max_atoms, double target_snr_db) {
   MPArgs a;
   a.dicts = p->d_dicts;
   a.pairs = p->d_pairs;
@@ -763,6 +774,18 @@ int mp_run(mp_plan* p, int64_t max_atoms, double target_snr_db, hipStream_t stre
   a.K = max_atoms;
   a.snr_db = target_snr_db;
   a.partner_gate = (p->flags & MP_CONJ_GATE_GAMMA) ? 1u : 0u;
+  a.pad2_ = 0;
+  a.reset_it = 0;
+  a.reset_db = 0.0;
+  return a;
+}
+
+int mp_run(mp_plan* p, int64_t max_atoms, double target_snr_db, hipStream_t stream) {
+  if (!p) return MP_E_ARG;
+  if (!p->analyzed) return MP_E_STATE;
+  int rc = ensure_cap(p, max_atoms, stream);
+  if (rc) return rc;
+  const MPArgs a = mp_args(p, max_atoms, target_snr_db);
   HCHK(hipEventRecord(p->ev[3], stream));
   HCHK(launch_mp(p->f64, p->nt, a, p->grid, stream));
   HCHK(hipEventRecord(p->ev[4], stream));
@@ -792,6 +815,74 @@ int mp_signal_info_get(const mp_plan* p, int32_t sig, mp_signal_info* out) {
   out->E0 = st.E0;
   out->E = st.E;
   return MP_OK;
+}
+
+int mp_run_resets(mp_plan* p, const void* x_dev, int32_t dtype, int64_t max_atoms, double target_snr_db,
+                  int64_t reset_it, double reset_db, hipStream_t stream) {
+  if (!p || !x_dev || (dtype != MP_DTYPE_F32 && dtype != MP_DTYPE_F64) || reset_it <= 0 || !(reset_db <= 0.0))
+    return MP_E_ARG;
+  if (!p->analyzed || p->ran) return MP_E_STATE;
+  int rc = ensure_cap(p, max_atoms, stream);
+  if (rc) return rc;
+  if (!p->d_res) {
+    std::vector<int64_t> roff((size_t)p->batch);
+    std::vector<SigDev> sr = p->hs;
+    int64_t tot = 0;
+    for (int s = 0; s < p->batch; ++s) {
+      roff[s] = tot;
+      sr[s].x_off = tot;
+      sr[s].L = sr[s].Lp;
+      tot += p->hs[s].Lp;
+    }
+    ACHK(dalloc(&p->d_res, (size_t)tot));
+    ACHK(dalloc(&p->d_roff, (size_t)p->batch));
+    ACHK(dalloc(&p->d_sigs_res, (size_t)p->batch));
+    ACHK(dalloc(&p->d_active, 1));
+    HCHK(hipMemcpy(p->d_roff, roff.data(), sizeof(int64_t) * p->batch, hipMemcpyHostToDevice));
+    HCHK(hipMemcpy(p->d_sigs_res, sr.data(), sizeof(SigDev) * p->batch, hipMemcpyHostToDevice));
+  }
+  {
+    MPArgs a = mp_args(p, max_atoms, target_snr_db);
+    a.reset_it = reset_it;
+    a.reset_db = reset_db;
+    HCHK(hipEventRecord(p->ev[3], stream));
+    HCHK(launch_reset_init(x_dev, dtype, p->d_sigs, p->batch, p->max_Lp, p->d_roff, p->d_res, stream));
+    const void* win = p->f64 ? (const void*)p->d_win64 : (const void*)p->d_win32;
+    for (;;) {
+      // inner loop: approximate MP on the current residual's coefficients
+      HCHK(launch_mp(p->f64, p->nt, a, p->grid, stream));
+      // solution and true residual, error, finished signals
+      HCHK(hipMemsetAsync(p->d_active, 0, sizeof(int), stream));
+      HCHK(launch_reset_update(p->d_atoms, p->d_sigs, p->d_state, p->d_dicts, p->d_win64, p->d_roff, p->d_res,
+                               p->batch, target_snr_db, max_atoms, p->d_active, stream));
+      int active = 0;
+      HCHK(hipMemcpyAsync(&active, p->d_active, sizeof(int), hipMemcpyDeviceToHost, stream));
+      // re-analysis of the residual: rho = D* r (also for the signals that just
+      // finished, so that their planes hold the analysis of the final residual)
+      for (int w = 0; w < p->W; ++w) {
+        const DictDev& D = p->hd[w];
+        const void* tw = p->f64 ? (const void*)(p->d_tw64 + D.tw_off) : (const void*)(p->d_tw32 + D.tw_off);
+        if (p->dft_fmt >= 0)
+          HCHK(launch_dgt_mfma(p->dft_fmt, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR,
+                               p->d_fprefix[w], p->batch, p->frames_total[w], p->d_win32 + D.win_off, tw,
+                               p->dft_n1[w], p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves,
+                               stream));
+        else
+          HCHK(launch_dgt(p->f64, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w],
+                          p->batch, p->frames_total[w], (const char*)win + D.win_off * (p->f64 ? 8 : 4), tw,
+                          p->d_planes, p->d_leaves, stream));
+      }
+      HCHK(hipStreamSynchronize(stream));
+      if (!active) break;
+    }
+    HCHK(hipEventRecord(p->ev[4], stream));
+  }
+  p->last_stream = stream;
+  p->last_K = max_atoms;
+  p->ran = true;
+  return MP_OK;
+fail:
+  return rc;
 }
 
 int mp_get_atoms(const mp_plan* p, int32_t sig, mp_atom* out_host, int64_t cap, int64_t* n_out) {

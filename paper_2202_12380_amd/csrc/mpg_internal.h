@@ -56,6 +56,10 @@ struct SigState {
   int64_t k;
   int32_t stop, pad;
   int64_t updated, blocks, groups;
+  // reset procedure (Alg. 2): true error and selections at the last reset
+  double Eout;
+  int64_t kout;
+  int32_t done, resets;
 };
 
 // Atom record, same layout as mp_atom.
@@ -83,7 +87,9 @@ struct MPArgs {
   int32_t n_groups_max, pad_;
   int64_t K;
   double snr_db;
-  uint32_t partner_gate;
+  uint32_t partner_gate, pad2_;
+  int64_t reset_it;            // > 0: inner loop of the reset procedure, at most reset_it selections
+  double reset_db;             // < 0: inner loop also ends when E <= Eout 10^(reset_db / 10)
 };
 
 }  // namespace mpg

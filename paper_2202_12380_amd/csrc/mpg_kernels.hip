@@ -388,6 +388,10 @@ __global__ void __launch_bounds__(256) k_energy(const XT* __restrict__ x, const 
     z.stop = 0;
     z.pad = 0;
     z.updated = z.blocks = z.groups = 0;
+    z.Eout = part[0];
+    z.kout = 0;
+    z.done = 0;
+    z.resets = 0;
     st[s] = z;
   }
 }
@@ -886,6 +890,7 @@ __device__ __forceinline__ int slot_to_group(const Tgt* tg, int W, int gs) {
 
 template <typename R, int NT, int SLOTS>
 __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane, int wave) {
+  if (A.reset_it > 0 && A.state[s].done) return;  // finished in an earlier round of the reset procedure
   using KO = KeyOps<R>;
   using KD = KeyDpp<R>;
   using Key = typename KO::Key;
@@ -973,7 +978,12 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
   const double E0 = st.E0;
   int64_t K = A.K > 0 ? A.K : S.Lp / 5;
   if (K > S.cap) K = S.cap;
-  const double Etarget = A.snr_db > 0.0 ? E0 * exp10(-A.snr_db / 10.0) : -__builtin_huge_val();
+  double Etarget = A.snr_db > 0.0 ? E0 * exp10(-A.snr_db / 10.0) : -__builtin_huge_val();
+  if (A.reset_it > 0) {
+    // inner loop of the reset procedure (Alg. 2)
+    K = min(K, st.kout + A.reset_it);
+    if (A.reset_db < 0.0) Etarget = fmax(Etarget, st.Eout * exp10(A.reset_db / 10.0));
+  }
   int stop = 0;
   int64_t c_upd = 0, c_blk = 0, c_grp = 0;
 
@@ -1393,6 +1403,7 @@ __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > 
 
 template <int NT, int SLOTS, int GL>
 __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lane, int wave) {
+  if (A.reset_it > 0 && A.state[s].done) return;  // finished in an earlier round of the reset procedure
   constexpr int NW = NT / 64;
   constexpr int LPL = GL / 64;                 // leaves of a group per lane
   constexpr int LOG_GL = GL == 128 ? 7 : 8;
@@ -1466,7 +1477,12 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   const double E0 = st.E0;
   int64_t K = A.K > 0 ? A.K : S.Lp / 5;
   if (K > S.cap) K = S.cap;
-  const double Etarget = A.snr_db > 0.0 ? E0 * exp10(-A.snr_db / 10.0) : -__builtin_huge_val();
+  double Etarget = A.snr_db > 0.0 ? E0 * exp10(-A.snr_db / 10.0) : -__builtin_huge_val();
+  if (A.reset_it > 0) {
+    // inner loop of the reset procedure (Alg. 2)
+    K = min(K, st.kout + A.reset_it);
+    if (A.reset_db < 0.0) Etarget = fmax(Etarget, st.Eout * exp10(A.reset_db / 10.0));
+  }
   int stop = 0;
   int64_t c_upd = 0, c_blk = 0, c_grp = 0;
 
@@ -1902,6 +1918,98 @@ __global__ void __launch_bounds__(1024) k_coefs(const AtomRec* __restrict__ atom
 }
 
 // --------------------------------------------------------------------------
+// Reset procedure (Alg. 2).  The true residual r = x - D c over the padded
+// length is kept in FP64, signal s at roff[s] (stride L_padded).  After each
+// inner loop the new selections are synthesized and subtracted in selection
+// order (one workgroup per signal; thread t owns the samples l = t mod T, so
+// no atomics), the residual's energy becomes the new error, and the signal is
+// finished when that true error reaches the target, the selection cap is
+// reached, the coefficients vanished, or the inner loop made no selection.
+
+template <typename XT>
+__global__ void __launch_bounds__(256) k_reset_init(const XT* __restrict__ x, const SigDev* __restrict__ sigs,
+                                                    const int64_t* __restrict__ roff, double* __restrict__ r) {
+  const int s = blockIdx.y;
+  const SigDev& S = sigs[s];
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < S.Lp; l += (int64_t)gridDim.x * 256)
+    r[roff[s] + l] = l < S.L ? (double)x[S.x_off + l] : 0.0;
+}
+
+__global__ void __launch_bounds__(1024) k_reset_update(const AtomRec* __restrict__ atoms,
+                                                       const SigDev* __restrict__ sigs, SigState* __restrict__ st,
+                                                       const DictDev* __restrict__ dicts,
+                                                       const double* __restrict__ win64,
+                                                       const int64_t* __restrict__ roff, double* __restrict__ r,
+                                                       double snr_db, int64_t K_total, int* __restrict__ active) {
+  __shared__ double part[1024];
+  const int s = blockIdx.x;
+  const SigState S0 = st[s];
+  if (S0.done) return;
+  const SigDev& S = sigs[s];
+  const int64_t T = blockDim.x, tid = threadIdx.x;
+  const int64_t Lp = S.Lp;
+  double* rs = r + roff[s];
+  const AtomRec* as = atoms + S.atom_base;
+  for (int64_t i = S0.kout; i < S0.k; ++i) {
+    const AtomRec at = as[i];
+    const DictDev D = dicts[at.w];
+    const double mult = (at.m != 0 && 2 * at.m != D.M) ? 2.0 : 1.0;
+    const double* g = win64 + D.win_off;
+    int64_t s0 = ((int64_t)at.n * D.a - D.gl / 2) % Lp;
+    if (s0 < 0) s0 += Lp;
+    // samples of the support by owner thread (l mod T); tp < split: l = s0 + tp, else l = s0 + tp - Lp
+    const int64_t split = D.gl < Lp - s0 ? D.gl : Lp - s0;
+    int64_t t0 = (tid - s0) % T;
+    if (t0 < 0) t0 += T;
+    for (int64_t tp = t0; tp < split; tp += T) {
+      const int64_t t = tp - D.gl / 2;
+      int64_t pi = ((int64_t)at.m * t) % D.M;
+      if (pi < 0) pi += D.M;
+      double sn, cs;
+      sincospi(2.0 * (double)pi / (double)D.M, &sn, &cs);
+      rs[s0 + tp] -= mult * g[tp] * (at.re * cs - at.im * sn);
+    }
+    for (int64_t l = tid; l < D.gl - split; l += T) {
+      const int64_t tp = l + Lp - s0;
+      const int64_t t = tp - D.gl / 2;
+      int64_t pi = ((int64_t)at.m * t) % D.M;
+      if (pi < 0) pi += D.M;
+      double sn, cs;
+      sincospi(2.0 * (double)pi / (double)D.M, &sn, &cs);
+      rs[l] -= mult * g[tp] * (at.re * cs - at.im * sn);
+    }
+  }
+  double acc = 0.0;
+  for (int64_t l = tid; l < Lp; l += T) acc += rs[l] * rs[l];
+  part[tid] = acc;
+  __syncthreads();
+  for (int h = (int)T / 2; h > 0; h >>= 1) {
+    if (tid < h) part[tid] += part[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double Eout = part[0];
+    const double Etg = snr_db > 0.0 ? S0.E0 * exp10(-snr_db / 10.0) : -__builtin_huge_val();
+    int64_t K = K_total > 0 ? K_total : Lp / 5;
+    if (K > S.cap) K = S.cap;
+    int stop = 0;
+    if (Eout <= Etg) stop = 2;
+    else if (S0.k >= K) stop = 1;
+    else if (S0.stop == 4) stop = 4;
+    else if (S0.k == S0.kout) stop = S0.stop ? S0.stop : 1;
+    SigState n = S0;
+    n.Eout = Eout;
+    n.E = Eout;
+    n.kout = S0.k;
+    n.resets = S0.resets + 1;
+    n.stop = stop;
+    n.done = stop != 0;
+    st[s] = n;
+    if (!stop) atomicAdd(active, 1);
+  }
+}
+
+// --------------------------------------------------------------------------
 // host-side launchers (called from mpg_api.cpp)
 
 #define CHK(x)                         \
@@ -2019,6 +2127,24 @@ hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs
     else DGT_MFMA(1, double);
   }
 #undef DGT_MFMA
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_init(const void* x, int dtype, const SigDev* sigs, int batch, int64_t max_Lp,
+                             const int64_t* roff, double* r, hipStream_t st) {
+  const int64_t nb = (max_Lp + 255) / 256;
+  const dim3 grid((unsigned)(nb < 4096 ? nb : 4096), (unsigned)batch);
+  if (dtype == 0)
+    k_reset_init<float><<<grid, 256, 0, st>>>((const float*)x, sigs, roff, r);
+  else
+    k_reset_init<double><<<grid, 256, 0, st>>>((const double*)x, sigs, roff, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_update(const AtomRec* atoms, const SigDev* sigs, SigState* st_, const DictDev* dicts,
+                               const double* win64, const int64_t* roff, double* r, int batch, double snr_db,
+                               int64_t K_total, int* active, hipStream_t st) {
+  k_reset_update<<<batch, 1024, 0, st>>>(atoms, sigs, st_, dicts, win64, roff, r, snr_db, K_total, active);
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ class mp_stats(C.Structure):
                 ("dgt_ms", C.c_double), ("group_leaves", C.c_int32), ("threads", C.c_int32)]
 
 
-EXPORTS = ["mp_plan_create", "mp_analyze", "mp_run", "mp_get_atoms", "mp_get_energy",
+EXPORTS = ["mp_plan_create", "mp_analyze", "mp_run", "mp_run_resets", "mp_get_atoms", "mp_get_energy",
            "mp_get_coefs", "mp_get_residual", "mp_resynth", "mp_signal_info_get",
            "mp_kernel_info_get", "mp_get_kernel", "mp_get_stats", "mp_plan_destroy",
            "mp_strerror"]
@@ -76,6 +76,7 @@ def lib():
                                  C.POINTER(vp)]
     L.mp_analyze.argtypes = [vp, vp, i32, vp]
     L.mp_run.argtypes = [vp, i64, dbl, vp]
+    L.mp_run_resets.argtypes = [vp, vp, i32, i64, dbl, i64, dbl, vp]
     L.mp_get_atoms.argtypes = [vp, i32, vp, i64, C.POINTER(C.c_int64)]
     L.mp_get_energy.argtypes = [vp, i32, vp, i64, C.POINTER(C.c_int64)]
     L.mp_get_coefs.argtypes = [vp, i32, i32, vp, vp]
@@ -133,6 +134,12 @@ def mp_analyze(plan: int, x_ptr: int, dtype: int, stream=None):
 
 def mp_run(plan: int, max_atoms: int = 0, target_snr_db: float = 0.0, stream=None):
     _chk(lib().mp_run(plan, int(max_atoms), float(target_snr_db), _stream(stream)), "mp_run")
+
+
+def mp_run_resets(plan: int, x_ptr: int, dtype: int, max_atoms: int = 0, target_snr_db: float = 0.0,
+                  reset_it: int = 1, reset_db: float = 0.0, stream=None):
+    _chk(lib().mp_run_resets(plan, x_ptr, dtype, int(max_atoms), float(target_snr_db), int(reset_it),
+                             float(reset_db), _stream(stream)), "mp_run_resets")
 
 
 def mp_signal_info_get(plan: int, sig: int) -> mp_signal_info:
@@ -233,6 +240,12 @@ class Plan:
 
     def run(self, max_atoms=0, target_snr_db=0.0, stream=None):
         mp_run(self.h, max_atoms, target_snr_db, stream)
+
+    def run_resets(self, max_atoms=0, target_snr_db=0.0, reset_it=1, reset_db=0.0, stream=None):
+        """Alg. 2 on the signal given to the last analyze()."""
+        import torch
+        dt = MP_DTYPE_F32 if self._x.dtype == torch.float32 else MP_DTYPE_F64
+        mp_run_resets(self.h, self._x.data_ptr(), dt, max_atoms, target_snr_db, reset_it, reset_db, stream)
 
     def info(self, sig=0):
         return mp_signal_info_get(self.h, sig)

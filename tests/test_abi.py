@@ -57,6 +57,7 @@ def test_strerror_and_argument_errors_without_gpu():
     # null handles
     assert L.mp_plan_destroy(None) == mpg.MP_E_ARG
     assert L.mp_run(None, 0, 0.0, None) == mpg.MP_E_ARG
+    assert L.mp_run_resets(None, None, 0, 0, 0.0, 1, 0.0, None) == mpg.MP_E_ARG
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

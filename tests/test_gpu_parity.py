@@ -260,3 +260,57 @@ def test_fresh_plan_after_freed_plans():
     x = np.random.default_rng(7).standard_normal(4096)
     _, ga = gpu_run(dicts, [x], 1e-4, K=200, flags=F64)
     assert_identical(ga[0], oracle_run(dicts, x, 1e-4, K=200))
+
+
+# --------------------------------------------------------------------------
+# reset procedure (Alg. 2)
+
+@pytest.mark.parametrize("eps,reset_it", [(5e-2, 200), (1e-3, 150)])
+def test_resets_fp64_identical(eps, reset_it):
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 64, 16, 64), (0, 256, 64, 256)]
+    L = 2000
+    x = np.random.default_rng(7).standard_normal(L)
+    plan = mpg.Plan(dicts, [L], eps, F64)
+    plan.analyze(torch.from_numpy(x).cuda())
+    plan.run_resets(900, 0.0, reset_it)
+    ga = plan.atoms(0)
+    orc = O.mp_resets(dicts, x, eps, K=900, reset_it=reset_it)
+    assert len(ga) == orc.n_atoms
+    assert np.array_equal(ga["w"], orc.w) and np.array_equal(ga["m"], orc.m) and np.array_equal(ga["n"], orc.n)
+    c = ga["re"] + 1j * ga["im"]
+    assert np.max(np.abs(c - orc.c)) <= 1e-9 * np.abs(orc.c).max()
+    assert np.max(np.abs(ga["E_after"] - orc.E)) <= 1e-12 * orc.E0
+    inf = plan.info(0)
+    assert inf.stop_reason == orc.stop_reason
+    assert abs(inf.E - orc.E_true[-1]) <= 1e-12 * orc.E0
+    # the planes hold the analysis of the final true residual
+    for w, d in enumerate(dicts):
+        ref = O.dgt(d, orc.residual)
+        got = plan.residual(0, w).cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_resets_fp32_batch_reach_true_target():
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 64, 16, 64), (0, 256, 64, 256)]
+    lens = [2048, 3000, 4096]
+    xs = [np.random.default_rng(20 + i).standard_normal(L).astype(np.float32) for i, L in enumerate(lens)]
+    plan = mpg.Plan(dicts, lens, 5e-2, 0)
+    plan.analyze(torch.from_numpy(np.concatenate(xs)).cuda())
+    plan.run_resets(100000, 30.0, 200, -6.0)
+    for s, x in enumerate(xs):
+        inf = plan.info(s)
+        assert inf.stop_reason == mpg.MP_STOP_SNR
+        assert inf.E <= 1e-3 * inf.E0
+        # the reported error is the energy of the true residual
+        xd = x.astype(np.float64)
+        Lp = inf.L_padded
+        yp = plan.resynth(s).cpu().numpy()
+        xp = np.zeros(Lp)
+        xp[:len(x)] = xd
+        assert abs(np.sum((xp - yp) ** 2) - inf.E) <= 1e-9 * inf.E0
+        orc = O.mp_resets(dicts, xd, 5e-2, K=100000, target_db=30.0, reset_it=200, reset_db=-6.0)
+        assert_tolerance(plan.atoms(s), orc)
