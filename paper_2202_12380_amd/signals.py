@@ -71,6 +71,16 @@ def workload(cid: int) -> Workload:
     raise ValueError(cid)
 
 
+def noise_study():
+    """The convergence experiment on noise (Sec. 6.1, Fig. 4): white Gaussian
+    noise of 6.04e6 samples (seeded stand-in for the paper's randn signal), the
+    three Blackman systems M = 512/1024/2048 with a = M/4, and the thresholds
+    1e-4, 1e-3, 5e-3, 1e-2.  Returns (dicts, thresholds, x)."""
+    dicts = [(BLACKMAN, g, g // 4, g) for g in (512, 1024, 2048)]
+    x = rng(6, 0).standard_normal(6_040_000)
+    return dicts, (1e-4, 1e-3, 5e-3, 1e-2), x
+
+
 def c3_lengths(batch: int, lo: int = 1 << 14, hi: int = 1 << 18, config_id: int = 3):
     g = rng(config_id, 1_000_000)
     u = g.uniform(np.log(lo), np.log(hi), size=batch)
