@@ -14,6 +14,7 @@ WIN_BLACKMAN = 0
 WIN_HANN = 1
 THR_REL = 1
 CONJ_GATE_GAMMA = 2
+PEDANTIC = 4
 
 STOP_K, STOP_SNR, STOP_ENEG, STOP_ZERO = 1, 2, 3, 4
 

@@ -328,16 +328,37 @@ typedef struct {
   int32_t MR;
   int64_t off; /* global index of (m = 0, n = 0) */
   double *re, *im;
-  double *fbest, *fsecond; /* per-frame top-2 of |rho|^2 */
+  double *fbest, *fsecond; /* per-frame top-2 of the selection score */
   int32_t *farg;           /* bin of the per-frame maximum */
+  /* pedantic selection: gamma(m) = <d, conj d> of bin m (0 at DC and Nyquist) */
+  const double *gre, *gim;
 } plane;
+
+/* Energy removed by projecting onto the real atom pair of coefficient rho
+ * with gamma = <d, conj d>, Eq. (projenfaster) with the adjusted coefficient
+ * of Eq. (dualatprod). */
+static double pair_energy(double rr, double ri, double gr, double gi) {
+  double nr = rr - (gr * rr - gi * ri);
+  double ni = ri - (-gr * ri - gi * rr);
+  double den = 1.0 - (gr * gr + gi * gi);
+  double cr = nr / den, ci = ni / den;
+  return 2.0 * (cr * cr + ci * ci + gr * (cr * cr - ci * ci) - 2.0 * gi * cr * ci);
+}
+
+/* Selection score of bin m: |rho|^2, or with pedantic selection the energy
+ * of the projection onto the pair (|rho|^2 at DC and Nyquist, which have no
+ * partner). */
+static double score(const plane *P, int32_t m, double r, double i) {
+  if (!P->gre || m == 0 || m == P->MR - 1) return r * r + i * i;
+  return pair_energy(r, i, P->gre[m], P->gim[m]);
+}
 
 static void frame_top2(plane *P, int64_t n) {
   double b = -1.0, s = -1.0;
   int32_t arg = 0;
   for (int32_t m = 0; m < P->MR; ++m) {
     double r = P->re[n * P->MR + m], i = P->im[n * P->MR + m];
-    double v = r * r + i * i;
+    double v = score(P, m, r, i);
     if (v > b) {
       s = b;
       b = v;
@@ -415,6 +436,24 @@ int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
       goto done;
     }
     orc_dgt(&d[w], xp, Lp, p->re, p->im);
+    p->gre = p->gim = NULL;
+    if (flags & ORC_PEDANTIC) {
+      /* gamma(m) = h_{w,w}(-2m mod M_w, 0) of the truncated auto kernel */
+      double *gr = calloc((size_t)p->MR, sizeof(double)), *gi = calloc((size_t)p->MR, sizeof(double));
+      if (!gr || !gi) {
+        free(gr), free(gi);
+        rc = ORC_E_NOMEM;
+        goto done;
+      }
+      pair_table *tw = &T[w * W + w];
+      for (int32_t m = 1; m + 1 < p->MR; ++m) {
+        int64_t mu = mod64(-2 * (int64_t)m, tw->Mmax);
+        gr[m] = tw->re[(int64_t)tw->D * tw->Mmax + mu];
+        gi[m] = tw->im[(int64_t)tw->D * tw->Mmax + mu];
+      }
+      p->gre = gr;
+      p->gim = gi;
+    }
     for (int64_t n = 0; n < p->N; ++n) frame_top2(p, n);
   }
 
@@ -437,7 +476,8 @@ int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
       reason = ORC_STOP_ENEG;
       break;
     }
-    /* selection: global maximum of |rho|^2, lowest global index on ties.
+    /* selection: global maximum of the score (|rho|^2, or the pair
+     * projection energy with pedantic selection), lowest global index on ties.
      * Frames are visited in increasing global index, so a strict '>' keeps
      * the first (lowest-index) maximum. */
     double best = -1.0, second = -1.0;
@@ -549,6 +589,7 @@ done:
     for (int32_t w = 0; w < W; ++w) {
       free(P[w].re), free(P[w].im), free(P[w].fbest), free(P[w].fsecond);
       free(P[w].farg);
+      free((void *)P[w].gre), free((void *)P[w].gim);
     }
   if (T)
     for (int32_t i = 0; i < W * W; ++i) free(T[i].re), free(T[i].im);

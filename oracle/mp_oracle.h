@@ -26,6 +26,7 @@ extern "C" {
 /* flags for orc_mp */
 #define ORC_THR_REL 1u         /* threshold relative to each kernel's peak   */
 #define ORC_CONJ_GATE_GAMMA 2u /* conjugate-partner update only if gamma!=0  */
+#define ORC_PEDANTIC 4u        /* select by the pair projection energy       */
 
 /* return codes */
 #define ORC_OK 0

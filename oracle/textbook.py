@@ -47,8 +47,25 @@ def dictionary(dicts, L: int):
     return np.stack(cols, axis=1), index
 
 
-def mp(dicts, x: np.ndarray, n_iter: int, stop_rel: float = 0.0):
-    """Returns (w, m, n, c, E) with E[k] = ||r_{k+1}||^2 after each selection."""
+def _pair_projection_energy(D, index, dicts, r):
+    """||P r||^2 for the projection of the real residual onto each atom's real
+    pair span{Re d, Im d} (span{d} at DC and Nyquist), by least squares per
+    atom: the criterion of pedantic selection (Sec. 5)."""
+    out = np.zeros(D.shape[1])
+    for p, (w, m, n) in enumerate(index):
+        d = D[:, p]
+        M = dicts[w][3]
+        A = d.real[:, None] if (m == 0 or 2 * m == M) else np.stack([d.real, d.imag], axis=1)
+        sol, *_ = np.linalg.lstsq(A, r, rcond=None)
+        u = A @ sol
+        out[p] = float(u @ u)
+    return out
+
+
+def mp(dicts, x: np.ndarray, n_iter: int, stop_rel: float = 0.0, pedantic: bool = False):
+    """Returns (w, m, n, c, E) with E[k] = ||r_{k+1}||^2 after each selection.
+    pedantic: select the atom whose pair projection removes the most energy
+    instead of the largest |<r, d>|."""
     x = np.asarray(x, np.float64)
     L = len(x)
     D, index = dictionary(dicts, L)
@@ -57,7 +74,7 @@ def mp(dicts, x: np.ndarray, n_iter: int, stop_rel: float = 0.0):
     ws, ms, ns, cs, Es = [], [], [], [], []
     for _ in range(n_iter):
         rho = D.conj().T @ r
-        mag = rho.real ** 2 + rho.imag ** 2
+        mag = _pair_projection_energy(D, index, dicts, r) if pedantic else rho.real ** 2 + rho.imag ** 2
         p = int(np.argmax(mag))
         w, m, n = index[p]
         M = dicts[w][3]

@@ -231,6 +231,28 @@ def test_p5_eps0_equals_textbook(dicts, L, seed):
     assert np.max(np.abs(r.E[:k] - E[:k])) < 1e-12 * r.E0
 
 
+@pytest.mark.parametrize("dicts,L,seed", [
+    ([(0, 32, 8, 32), (0, 64, 16, 64)], 256, 31),
+    ([(1, 16, 4, 16), (0, 32, 8, 32)], 128, 32),
+])
+def test_p5_pedantic_eps0_equals_textbook_pedantic(dicts, L, seed):
+    # pedantic selection (Sec. 5): the atom whose real-pair projection removes
+    # the most energy; the textbook side measures that energy by least squares
+    # on each atom's pair, the oracle by Eq. (projenfaster) on its coefficients
+    x = np.random.default_rng(seed).standard_normal(L)
+    x += 3.0  # a DC component, where the pair score differs most from |rho|^2
+    n_it = 60
+    r = O.mp(dicts, x, 0.0, K=n_it, flags=O.PEDANTIC)
+    w, m, n, c, E = T.mp(dicts, x, n_it, pedantic=True)
+    assert r.n_atoms == n_it == len(w)
+    assert np.array_equal(r.w, w) and np.array_equal(r.m, m) and np.array_equal(r.n, n)
+    assert np.max(np.abs(r.c - c) / np.abs(c)) < 1e-11
+    assert np.max(np.abs(r.E - E)) < 1e-12 * r.E0
+    # the plain selection takes a different path on this signal
+    q = O.mp(dicts, x, 0.0, K=n_it)
+    assert not (np.array_equal(q.w, r.w) and np.array_equal(q.m, r.m) and np.array_equal(q.n, r.n))
+
+
 # --------------------------------------------------------------------------
 # P6: invariants at eps > 0
 
