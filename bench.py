@@ -78,7 +78,8 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--plan-flags", type=lambda v: int(v, 0), default=0,
-                    help="extra plan flags for --study noise (e.g. 0x20: conjugate partner only when gamma != 0)")
+                    help="extra plan flags (e.g. 0x100: pedantic selection, 0x20: conjugate partner only "
+                         "when gamma != 0, 0x40 / 0x80: split FP16 / BF16 DFT)")
     ap.add_argument("--eps", type=float, action="append", default=None,
                     help="restrict --study noise to these thresholds")
     ap.add_argument("--study", choices=["precision", "noise"], default=None,
@@ -128,7 +129,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---- batched FP32 path ----
-    plan = mpg.Plan(wl.dicts, lengths, wl.eps, 0)
+    plan = mpg.Plan(wl.dicts, lengths, wl.eps, args.plan_flags)
     x = torch.from_numpy(np.concatenate(xs).astype(np.float32)).to(dev)
     log("plan built; warmup")
     for _ in range(args.warmup):
@@ -238,6 +239,7 @@ def main():
             "batch": len(lengths), "total_samples": int(sum(lengths)), "atoms_per_step": atoms,
             "stop_reasons": {"K": stops[1], "snr": stops[2], "E<0": stops[3], "zero": stops[4]},
             "min_snr_db": float(min(snr_reached)),
+            "plan_flags": args.plan_flags,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,

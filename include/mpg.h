@@ -62,6 +62,11 @@ extern "C" {
  * hi*hi + hi*lo + lo*hi accumulated in FP32); systems need M <= 16384. */
 #define MP_DFT_F16SPLIT 0x40u    /* FP16 pairs                                      */
 #define MP_DFT_BF16SPLIT 0x80u   /* BF16 pairs                                      */
+/* Pedantic selection (Sec. 5): choose the atom whose real-pair projection
+ * removes the most energy (Eq. projenfaster with the adjusted coefficient of
+ * Eq. dualatprod) instead of the largest |rho|^2; DC and Nyquist atoms, which
+ * have no partner, score |rho|^2. */
+#define MP_PEDANTIC 0x100u
 
 /* ---- input sample types for mp_analyze / output types for mp_resynth ---- */
 #define MP_DTYPE_F32 0
@@ -129,7 +134,8 @@ typedef struct {
  * FP64, every truncated cross-kernel h_{w,v} on its common grid (Sec. 4.1,
  * 4.2; threshold Eq. truncgram, absolute unless MP_THR_REL) plus FP32 copies.
  * kernel_tol is the threshold epsilon (> 0).  flags: MP_PREC_*, MP_THR_REL,
- * MP_CONJ_GATE_GAMMA, at most one MP_DFT_* (not with MP_PREC_F64).  Uses the
+ * MP_CONJ_GATE_GAMMA, MP_PEDANTIC, at most one MP_DFT_* (not with
+ * MP_PREC_F64).  Uses the
  * current HIP device; blocks until the kernels are built.  *out receives the
  * plan.  MP_E_LIMIT: a frame's FFT exceeds the LDS of one workgroup (M/2
  * complex entries; twice that for MP_DFT_*), or the signal's tree groups do

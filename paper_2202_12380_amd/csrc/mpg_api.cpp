@@ -33,10 +33,11 @@ hipError_t launch_dft_tables(int fmt, int N, int Np, uint16_t* out, hipStream_t 
 hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a, int M,
                            int MR, const int64_t* frame_prefix, int batch, int64_t frames, const float* win,
                            const void* tw, int N1, int N2, const uint16_t* F1, const uint16_t* F2, void* planes,
-                           void* leaves, hipStream_t st);
+                           void* leaves, const void* gam, int pedantic, hipStream_t st);
 hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
-                      const void* win, const void* tw, void* planes, void* leaves, hipStream_t st);
+                      const void* win, const void* tw, void* planes, void* leaves, const void* gam, int pedantic,
+                      hipStream_t st);
 size_t leaf_bytes(bool f64);
 size_t mp_shmem_bytes(bool f64, int nt, int G, int n_groups_max);
 hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st);
@@ -287,7 +288,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
   *out = nullptr;
   if (!dicts || !L || W < 1 || W > MAXW || batch < 1 || batch > (1 << 20)) return MP_E_ARG;
   if (!(kernel_tol >= 0.0 && kernel_tol < 1.0)) return MP_E_ARG;
-  if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA | MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT))
+  if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA | MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT | MP_PEDANTIC))
     return MP_E_ARG;
   const uint32_t dftf = flags & (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT);
   if (dftf == (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT) || (dftf && (flags & MP_PREC_F64))) return MP_E_ARG;
@@ -735,11 +736,11 @@ int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream)
     if (p->dft_fmt >= 0)
       HCHK(launch_dgt_mfma(p->dft_fmt, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w],
                            p->batch, p->frames_total[w], p->d_win32 + D.win_off, tw, p->dft_n1[w],
-                           p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves, stream));
+                           p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
     else
       HCHK(launch_dgt(p->f64, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w], p->batch,
                       p->frames_total[w], (const char*)win + D.win_off * (p->f64 ? 8 : 4), tw, p->d_planes,
-                      p->d_leaves, stream));
+                      p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
   }
   HCHK(hipEventRecord(p->ev[1], stream));
   HCHK(hipEventRecord(p->ev[2], stream));
@@ -774,7 +775,7 @@ static MPArgs mp_args(const mp_plan* p, int64_t max_atoms, double target_snr_db)
   a.K = max_atoms;
   a.snr_db = target_snr_db;
   a.partner_gate = (p->flags & MP_CONJ_GATE_GAMMA) ? 1u : 0u;
-  a.pad2_ = 0;
+  a.pedantic = (p->flags & MP_PEDANTIC) ? 1u : 0u;
   a.reset_it = 0;
   a.reset_db = 0.0;
   return a;
@@ -866,11 +867,11 @@ int mp_run_resets(mp_plan* p, const void* x_dev, int32_t dtype, int64_t max_atom
           HCHK(launch_dgt_mfma(p->dft_fmt, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR,
                                p->d_fprefix[w], p->batch, p->frames_total[w], p->d_win32 + D.win_off, tw,
                                p->dft_n1[w], p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves,
-                               stream));
+                               (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
         else
           HCHK(launch_dgt(p->f64, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w],
                           p->batch, p->frames_total[w], (const char*)win + D.win_off * (p->f64 ? 8 : 4), tw,
-                          p->d_planes, p->d_leaves, stream));
+                          p->d_planes, p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
       }
       HCHK(hipStreamSynchronize(stream));
       if (!active) break;

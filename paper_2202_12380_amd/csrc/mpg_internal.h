@@ -87,7 +87,7 @@ struct MPArgs {
   int32_t n_groups_max, pad_;
   int64_t K;
   double snr_db;
-  uint32_t partner_gate, pad2_;
+  uint32_t partner_gate, pedantic;  // pedantic: select by the pair projection energy (Sec. 5)
   int64_t reset_it;            // > 0: inner loop of the reset procedure, at most reset_it selections
   double reset_db;             // < 0: inner loop also ends when E <= Eout 10^(reset_db / 10)
 };

@@ -243,6 +243,21 @@ __device__ __forceinline__ uint64_t row_max_bits<double>(uint64_t b) {
   b = max_dpp64<0x128>(b);
   return b;
 }
+// Selection score of a coefficient: |rho|^2, or with pedantic selection
+// (Sec. 5) the energy removed by projecting onto its real atom pair,
+// Eq. (projenfaster) with the adjusted coefficient of Eq. (dualatprod) and
+// gamma = <d, conj d> of its bin; DC and Nyquist bins (no partner) keep
+// |rho|^2.  Never negative, so the bits order like the values.
+template <typename R>
+__device__ __forceinline__ R sel_score(R re, R im, Cx<R> g, bool pedantic_pair) {
+  if (!pedantic_pair) return re * re + im * im;
+  const R nr = re - (g.re * re - g.im * im), ni = im - (-g.re * im - g.im * re);
+  const R den = (R)1 - (g.re * g.re + g.im * g.im);
+  const R cr = nr / den, ci = ni / den;
+  const R e = (R)2 * (cr * cr + ci * ci + g.re * (cr * cr - ci * ci) - (R)2 * g.im * cr * ci);
+  return e > (R)0 ? e : (R)0;
+}
+
 // Wave maximum of keys, returned uniformly.  FP32 keys: maximum of the value
 // word, then of the inverted index among lanes holding that value.
 template <typename R>
@@ -413,7 +428,8 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
                                              int w, int gl, int a, int M, int logM, int MR,
                                              const int64_t* __restrict__ frame_prefix, int batch,
                                              const R* __restrict__ win, const Cx<R>* __restrict__ tw,
-                                             Cx<R>* __restrict__ planes, Leaf<R>* __restrict__ leaves) {
+                                             Cx<R>* __restrict__ planes, Leaf<R>* __restrict__ leaves,
+                                             const Cx<R>* __restrict__ gam, int pedantic) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem_raw);
   const int H = M >> 1, logH = logM - 1;
@@ -488,7 +504,8 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
       v.im = ei + (t.re * oi + t.im * or_);
       out[m] = v;
     }
-    const R val = v.re * v.re + v.im * v.im;
+    const bool ped = pedantic && valid && m != 0 && m != H;
+    const R val = sel_score<R>(v.re, v.im, ped ? gam[m] : Cx<R>{(R)0, (R)0}, ped);
     const uint64_t bits = valid ? val_bits(val) : 0ull;
     const uint64_t rm = row_max_bits<R>(bits);
     const uint64_t bal = __ballot(valid && bits == rm);
@@ -606,7 +623,8 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
                                                   const float* __restrict__ win, const Cx<float>* __restrict__ tw,
                                                   int N1, int N2, const uint16_t* __restrict__ F1,
                                                   const uint16_t* __restrict__ F2, Cx<float>* __restrict__ planes,
-                                                  Leaf<float>* __restrict__ leaves) {
+                                                  Leaf<float>* __restrict__ leaves,
+                                                  const Cx<float>* __restrict__ gam, int pedantic) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int H = M >> 1;
   Cx<float>* buf = reinterpret_cast<Cx<float>*>(smem_raw);  // z, then B
@@ -776,7 +794,8 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
       v.im = ei + (t.re * oi + t.im * or_);
       out[m] = v;
     }
-    const float val = v.re * v.re + v.im * v.im;
+    const bool ped = pedantic && valid && m != 0 && m != H;
+    const float val = sel_score<float>(v.re, v.im, ped ? gam[m] : Cx<float>{0.0f, 0.0f}, ped);
     const uint64_t bits = valid ? val_bits(val) : 0ull;
     const uint64_t rm = row_max_bits<float>(bits);
     const uint64_t bal = __ballot(valid && bits == rm);
@@ -1028,7 +1047,7 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
           T.MR = P.MR; T.N = P.N; T.off = P.off; T.lbase = P.lbase;
           T.lpf = P.lpf; T.Mmax = P.Mmax; T.rw = P.rw; T.kr = kk * P.rv;
           T.mulo = P.mulo; T.muhi = P.muhi; T.width = P.width; T.sw = P.sw;
-          T.dbox = P.dbox; T.tab = P.tab; T.pad[0] = T.pad[1] = 0;
+          T.dbox = P.dbox; T.tab = P.tab; T.pad[0] = (int32_t)dc[lane].gamma_off; T.pad[1] = 0;
           T.cph = (kk * P.amin) & vmask;
           T.nlo = 0; T.nF = 0; T.dlo = 0; T.ilo = 0; T.bpf = 1;
           T.gA_lo = T.gA_n = T.gB_lo = 0;
@@ -1136,17 +1155,17 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
     Cx<R> cc = {(R)0, (R)0};
     bool partner = false;
     for (int round = 0;; ++round) {
-      Cx<R> r[SLOTS], h1[SLOTS], h2[SLOTS], ph[SLOTS];
+      Cx<R> r[SLOTS], h1[SLOTS], h2[SLOTS], ph[SLOTS], gg[SLOTS];
       int ee[SLOTS], lfi[SLOTS], gsl[SLOTS];
-      bool act[SLOTS], rowok[SLOTS], vld[SLOTS], chg[SLOTS];
+      bool act[SLOTS], rowok[SLOTS], vld[SLOTS], chg[SLOTS], pp[SLOTS];
       int cw = -1;
       Tgt T;
 #pragma unroll
       for (int sl = 0; sl < SLOTS; ++sl) {
-        r[sl] = h1[sl] = h2[sl] = Cx<R>{(R)0, (R)0};
+        r[sl] = h1[sl] = h2[sl] = gg[sl] = Cx<R>{(R)0, (R)0};
         ph[sl] = Cx<R>{(R)1, (R)0};
         ee[sl] = lfi[sl] = gsl[sl] = 0;
-        act[sl] = rowok[sl] = vld[sl] = chg[sl] = false;
+        act[sl] = rowok[sl] = vld[sl] = chg[sl] = pp[sl] = false;
         const int base4 = ((round * SLOTS + sl) * NW + wave) * 4;
         if (base4 >= T_items) continue;  // wave-uniform
         act[sl] = true;
@@ -1182,6 +1201,8 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
         if (!ok || m >= T.MR) continue;
         vld[sl] = true;
         r[sl] = rho[e];
+        pp[sl] = A.pedantic && m != 0 && m != T.MR - 1;
+        if (pp[sl]) gg[sl] = gams[T.pad[0] + m];
         const int d = T.dlo + f * T.sw;  // delta = Delta / a_min, in [-dbox, dbox]
         const int mm = T.Mmax - 1;
         int mu1 = (m * T.rw - T.kr) & mm;
@@ -1259,7 +1280,7 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
             rho[ee[sl]] = r[sl];
           }
         }
-        const R val = r[sl].re * r[sl].re + r[sl].im * r[sl].im;
+        const R val = sel_score<R>(r[sl].re, r[sl].im, gg[sl], pp[sl]);
         const uint64_t bits = vld[sl] ? val_bits(val) : 0ull;
         const uint64_t rm = row_max_bits<R>(bits);
         const uint64_t bal = __ballot(vld[sl] && bits == rm);
@@ -1420,6 +1441,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   const Cx<float>* gams = reinterpret_cast<const Cx<float>*>(A.gammas);
   const Cx<float>* roots = reinterpret_cast<const Cx<float>*>(A.roots);
   const int rid = lane >> LOG_ROW, rl = lane & (ROW - 1);
+  const bool pedantic = A.pedantic != 0;
 
   // LDS carve-up (must match mp32_lds_bytes)
   uint64_t* gkey = reinterpret_cast<uint64_t*>(smem);
@@ -1530,7 +1552,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
         T.k1 = kr + P.mulo;
         T.k2 = P.mulo - kr;
         T.mspan = P.muhi - P.mulo;
-        T.pad[0] = T.pad[1] = T.pad[2] = 0;
+        T.pad[0] = d_gam;  // gamma(m) of target u's bins (lane u holds system u's offset)
+        T.pad[1] = T.pad[2] = 0;
         const int jsv = j * P.sv;
         const int nlo = -((P.dbox - jsv) >> P.sw_sh), nhi = (jsv + P.dbox) >> P.sw_sh;
         const int half = P.M >> 1;
@@ -1688,8 +1711,9 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     const int q_begin = wave * chunk, q_end = min(nslots, q_begin + chunk);
     for (int qb = q_begin; qb < q_end; qb += SLOTS) {
       const int nact = min(SLOTS, q_end - qb);
-      Cx<float> r[SLOTS], h1[SLOTS], h2[SLOTS], ph[SLOTS];
-      uint32_t ee[SLOTS], lfi[SLOTS], fl[SLOTS];  // fl bit 0: row in grid, 1: bin valid, 2/3: term 1/2 in box
+      Cx<float> r[SLOTS], h1[SLOTS], h2[SLOTS], ph[SLOTS], gg[SLOTS];
+      // fl bit 0: row in grid, 1: bin valid, 2/3: term 1/2 in box, 4: pedantic score
+      uint32_t ee[SLOTS], lfi[SLOTS], fl[SLOTS];
       int gsl[SLOTS];
       {
         int cw = -1;
@@ -1728,7 +1752,10 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
           ph[sl] = roots[root_off + ((T.ph0 + (uint32_t)f * T.phs) & vmask)];
           ee[sl] = e;
           lfi[sl] = (uint32_t)li;
-          fl[sl] = (ok ? 1u : 0u) | (vl ? 2u : 0u) | (in1 ? 4u : 0u) | (in2 ? 8u : 0u);
+          const bool pb = pedantic && vl && m != 0 && m != T.MR - 1;
+          gg[sl] = Cx<float>{0.0f, 0.0f};
+          if (pedantic) gg[sl] = gams[pb ? (uint32_t)(T.pad[0] + m) : 0u];
+          fl[sl] = (ok ? 1u : 0u) | (vl ? 2u : 0u) | (in1 ? 4u : 0u) | (in2 ? 8u : 0u) | (pb ? 16u : 0u);
           // touched-group slot of the row's group
           const int g = li >> LOG_GL;
           gsl[sl] = T.slot_base + ((g >= T.gA_lo && g < T.gA_lo + T.gA_n) ? g - T.gA_lo : T.gA_n + g - T.gB_lo);
@@ -1753,7 +1780,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
         rv.im -= ui;
         if (nz) rho[ee[sl]] = rv;
         const bool vl = (fs & 2u) != 0;
-        const float val = rv.re * rv.re + rv.im * rv.im;
+        const float val = sel_score<float>(rv.re, rv.im, gg[sl], (fs & 16u) != 0);
         const uint32_t bits = vl ? __float_as_uint(val) : 0u;
         const uint32_t rm = (uint32_t)row_max_bits<float>(bits);
         const uint64_t bal = __ballot(vl && bits == rm);
@@ -2059,7 +2086,8 @@ hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch
 
 hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
-                      const void* win, const void* tw, void* planes, void* leaves, hipStream_t st) {
+                      const void* win, const void* tw, void* planes, void* leaves, const void* gam, int pedantic,
+                      hipStream_t st) {
   if (frames <= 0) return hipSuccess;
   int logM = 0;
   while ((1 << logM) < M) ++logM;
@@ -2073,20 +2101,24 @@ hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, in
     if (dtype == 0)
       k_dgt<double, float><<<grid, 256, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                   batch, (const double*)win, (const Cx<double>*)tw,
-                                                  (Cx<double>*)planes, (Leaf<double>*)leaves);
+                                                  (Cx<double>*)planes, (Leaf<double>*)leaves,
+                                                  (const Cx<double>*)gam, pedantic);
     else
       k_dgt<double, double><<<grid, 256, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                    batch, (const double*)win, (const Cx<double>*)tw,
-                                                   (Cx<double>*)planes, (Leaf<double>*)leaves);
+                                                   (Cx<double>*)planes, (Leaf<double>*)leaves,
+                                                  (const Cx<double>*)gam, pedantic);
   } else {
     if (dtype == 0)
       k_dgt<float, float><<<grid, 256, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                  batch, (const float*)win, (const Cx<float>*)tw,
-                                                 (Cx<float>*)planes, (Leaf<float>*)leaves);
+                                                 (Cx<float>*)planes, (Leaf<float>*)leaves,
+                                                 (const Cx<float>*)gam, pedantic);
     else
       k_dgt<float, double><<<grid, 256, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                   batch, (const float*)win, (const Cx<float>*)tw,
-                                                  (Cx<float>*)planes, (Leaf<float>*)leaves);
+                                                  (Cx<float>*)planes, (Leaf<float>*)leaves,
+                                                 (const Cx<float>*)gam, pedantic);
   }
   return hipGetLastError();
 }
@@ -2103,7 +2135,7 @@ hipError_t launch_dft_tables(int fmt, int N, int Np, uint16_t* out, hipStream_t 
 hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a, int M,
                            int MR, const int64_t* frame_prefix, int batch, int64_t frames, const float* win,
                            const void* tw, int N1, int N2, const uint16_t* F1, const uint16_t* F2, void* planes,
-                           void* leaves, hipStream_t st) {
+                           void* leaves, const void* gam, int pedantic, hipStream_t st) {
   if (frames <= 0) return hipSuccess;
   const size_t sh = (size_t)M * 8;  // z / B and Z, H complex FP32 each
   if (sh > 160 * 1024) return hipErrorInvalidValue;
@@ -2117,7 +2149,7 @@ hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs
       CHK(hipFuncSetAttribute((const void*)k_dgt_mfma<F, XT>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
                               (int)sh));                                                                    \
     k_dgt_mfma<F, XT><<<grid, 256, sh, st>>>((const XT*)x, sigs, w, gl, a, M, MR, frame_prefix, batch, win,  \
-                                             twc, N1, N2, F1, F2, pl, lv);                                  \
+                                             twc, N1, N2, F1, F2, pl, lv, (const Cx<float>*)gam, pedantic); \
   } while (0)
   if (fmt == 0) {
     if (dtype == 0) DGT_MFMA(0, float);

@@ -20,6 +20,7 @@ MP_WIN_BLACKMAN, MP_WIN_HANN = 0, 1
 MP_PREC_F32, MP_PREC_F64 = 0x0, 0x1
 MP_THR_REL, MP_CONJ_GATE_GAMMA = 0x10, 0x20
 MP_DFT_F16SPLIT, MP_DFT_BF16SPLIT = 0x40, 0x80
+MP_PEDANTIC = 0x100
 MP_DTYPE_F32, MP_DTYPE_F64 = 0, 1
 MP_STOP_NONE, MP_STOP_K, MP_STOP_SNR, MP_STOP_ENEG, MP_STOP_ZERO = range(5)
 

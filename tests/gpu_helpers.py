@@ -28,6 +28,8 @@ def oracle_run(dicts, x, eps, K=0, snr_db=0.0, flags=0, x_dtype=np.float64, cap=
         oflags |= O.THR_REL
     if flags & 0x20:
         oflags |= O.CONJ_GATE_GAMMA
+    if flags & 0x100:
+        oflags |= O.PEDANTIC
     return O.mp(dicts, xv, eps, K=K, target_db=snr_db, flags=oflags, cap=cap)
 
 

@@ -139,6 +139,30 @@ def test_mp_fp64_identical(dicts, L, eps, K):
     assert_identical(ga[0], orc)
 
 
+@pytest.mark.parametrize("dicts,L,eps,K,dc", [
+    ([(0, 64, 16, 64), (0, 128, 32, 128)], 2048, 1e-4, 400, 0.0),
+    ([(0, 64, 16, 64), (0, 128, 32, 128)], 2048, 1e-4, 400, 3.0),   # strong DC: scores differ most
+    ([(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)], 16384, 1e-4, 600, 0.5),
+])
+def test_mp_pedantic_fp64_identical(dicts, L, eps, K, dc):
+    _torch()
+    x = np.random.default_rng(L + K + 1).standard_normal(L) + dc
+    _, ga = gpu_run(dicts, [x], eps, K=K, flags=F64 | 0x100)
+    orc = oracle_run(dicts, x, eps, K=K, flags=0x100)
+    assert_identical(ga[0], orc)
+
+
+def test_mp_pedantic_fp32_batch():
+    _torch()
+    dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)]
+    lens = [16384, 9000, 20000]
+    xs = [(S.audio_like(L, S.rng(79, i)) + 0.05).astype(np.float32) for i, L in enumerate(lens)]
+    _, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=0x100)
+    for i, x in enumerate(xs):
+        orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32, flags=0x100)
+        assert_tolerance(ga[i], orc)
+
+
 # --------------------------------------------------------------------------
 # MP loop, FP32: identical up to the first small top-2 gap, E within 1e-5 ||x||^2
 
