@@ -488,8 +488,9 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       for (int w = 0; w < W; ++w)
         HCHK(launch_roots(p->hd[w].M, p->hd[w].M / 2, -1, p->d_tw64 + p->hd[w].tw_off,
                           p->d_tw32 + p->hd[w].tw_off, st));
-      ACHK(dalloc(&p->d_gam64, (size_t)gamoff));
-      ACHK(dalloc(&p->d_gam32, (size_t)gamoff));
+      // one entry past the end: the FP32 loop reads gamma of two adjacent bins
+      ACHK(dalloc(&p->d_gam64, (size_t)gamoff + 1));
+      ACHK(dalloc(&p->d_gam32, (size_t)gamoff + 1));
       // exp(+2 pi i j / M), j < M: the phases exp(2 pi i k Delta / M_v) of Eq. (hkj)
       ACHK(dalloc(&p->d_root64, (size_t)rootoff));
       ACHK(dalloc(&p->d_root32, (size_t)rootoff));
@@ -640,6 +641,8 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
           g32.push_back(make_float2((float)re, (float)im));
         }
       }
+      g64.push_back(make_double2(0.0, 0.0));
+      g32.push_back(make_float2(0.0f, 0.0f));
       HCHK(hipMemcpy(p->d_gam64, g64.data(), g64.size() * sizeof(double2), hipMemcpyHostToDevice));
       HCHK(hipMemcpy(p->d_gam32, g32.data(), g32.size() * sizeof(float2), hipMemcpyHostToDevice));
     }
@@ -654,8 +657,9 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     ACHK(dalloc(&p->d_state, (size_t)batch));
     HCHK(hipMemset(p->d_state, 0, sizeof(SigState) * batch));
     const size_t cb = p->f64 ? 16 : 8;
-    HCHK(hipMalloc(&p->d_planes, (size_t)p->total_coef * cb));
-    HCHK(hipMemset(p->d_planes, 0, (size_t)p->total_coef * cb));
+    // one coefficient past the end: the FP32 loop reads two adjacent bins
+    HCHK(hipMalloc(&p->d_planes, (size_t)(p->total_coef + 1) * cb));
+    HCHK(hipMemset(p->d_planes, 0, (size_t)(p->total_coef + 1) * cb));
     HCHK(hipMalloc(&p->d_leaves, (size_t)std::max<int64_t>(p->total_leaves, 1) * leaf_bytes(p->f64)));
     // padding leaves (systems rounded up to whole groups) are never written by
     // the analysis and must read as empty keys

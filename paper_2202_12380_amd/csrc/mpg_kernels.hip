@@ -1374,16 +1374,22 @@ __global__ void __launch_bounds__(NT) k_mp(MPArgs A) {
 // kept differently:
 //   leaves (16 bins of one frame, 8-byte keys, global memory)
 //     -> groups of GL leaves (keys in LDS) -> root (reduced per selection).
-// A touched group whose maximum leaf lies outside the update grid can only
-// gain from the update, so the row leaders raise its key with an LDS atomic
-// maximum.  A group whose maximum leaf is rewritten ("dirty", always the
-// group of the selected atom) is re-reduced after the update: its old leaves
+// Every group touched by the update is re-reduced after it: its old leaves
 // are preloaded into registers while the rows are processed, the rewritten
 // ones go through an LDS scratch, and the owner wave merges the two.
 //
-// Per selection: wave 0 (root, decode, target grids, dirty groups) | barrier |
-// all waves (rows: loads, adjustment, update, leaves) | barrier | owners merge
-// dirty groups | barrier.
+// Selection is pipelined.  The keys of the groups an update does not touch
+// cannot change in it, so while the other waves update the rows of atom k,
+// wave 0 takes the maximum over those groups as the candidate atom k+1 and
+// lays out its target grids and adjusted coefficient in a second buffer.
+// After the merge one key comparison decides: the candidate is atom k+1
+// unless a touched group now holds a larger key, in which case wave 0 decodes
+// that key (the maximum over the touched groups, gathered by the merge) before
+// the next update.  The selections are the same as with a serial root scan.
+//
+// Per selection: all waves (rows; wave 0 first builds the candidate) |
+// barrier | owners merge touched groups | barrier | [refuted candidate:
+// wave 0 selects | barrier].
 
 constexpr uint64_t KEY_SENT = ~0ull;     // scratch entry not written
 
@@ -1410,6 +1416,7 @@ struct __align__(16) It32 {
   double Et;                         // energy decrease of the selection
   int32_t ibase[MAXW];               // first row item of each target
   int32_t sbase[MAXW];               // first touched-group slot of each target
+  int32_t gown[16];                  // group of touched-group slot gs < 2 NW (merged from registers)
 };
 
 __host__ __device__ constexpr int mp32_groups_padded(int n_groups) { return (n_groups + 511) & ~511; }
@@ -1417,10 +1424,21 @@ __host__ __device__ constexpr int mp32_groups_padded(int n_groups) { return (n_g
 template <int NT, int GL>
 __host__ __device__ constexpr size_t mp32_lds_bytes(int n_groups_max) {
   return (size_t)mp32_groups_padded(n_groups_max) * 8 + (size_t)(2 * (NT / 64)) * GL * 8 +
-         (size_t)MAXW * sizeof(RowT) + (size_t)MAXW * MAXW * sizeof(PairC) + sizeof(It32) + 64;
+         (size_t)(2 * MAXW) * sizeof(RowT) + (size_t)MAXW * MAXW * sizeof(PairC) + 2 * sizeof(It32) + 4 * 8 + 64;
 }
 
 __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+// Two adjacent complex FP32 values (16 bytes, 8-byte aligned).
+struct __align__(8) C4f {
+  float x, y, z, w;
+};
+__device__ __forceinline__ C4f ld_c4(const Cx<float>* q) {
+  C4f v;
+  __builtin_memcpy(&v, q, sizeof(C4f));
+  return v;
+}
+__device__ __forceinline__ void st_c4(Cx<float>* q, const C4f& v) { __builtin_memcpy(q, &v, sizeof(C4f)); }
 
 template <int NT, int SLOTS, int GL>
 __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lane, int wave) {
@@ -1440,15 +1458,18 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   const Cx<float>* tabs = reinterpret_cast<const Cx<float>*>(A.tabs);
   const Cx<float>* gams = reinterpret_cast<const Cx<float>*>(A.gammas);
   const Cx<float>* roots = reinterpret_cast<const Cx<float>*>(A.roots);
-  const int rid = lane >> LOG_ROW, rl = lane & (ROW - 1);
+  const int rid8 = lane >> 3, rl8 = lane & 7;
   const bool pedantic = A.pedantic != 0;
 
   // LDS carve-up (must match mp32_lds_bytes)
   uint64_t* gkey = reinterpret_cast<uint64_t*>(smem);
   uint64_t* scratch = gkey + ngp_max;
-  RowT* tg = reinterpret_cast<RowT*>(scratch + NPRE * GL);
-  PairC* pc = reinterpret_cast<PairC*>(tg + MAXW);
-  It32* it = reinterpret_cast<It32*>(pc + MAXW * MAXW);
+  RowT* tg2 = reinterpret_cast<RowT*>(scratch + NPRE * GL);     // two buffers of MAXW
+  PairC* pc = reinterpret_cast<PairC*>(tg2 + 2 * MAXW);
+  It32* it2 = reinterpret_cast<It32*>(pc + MAXW * MAXW);        // two buffers
+  uint64_t* ckey = reinterpret_cast<uint64_t*>(it2 + 2);        // [b]: candidate key of buffer b
+  uint64_t* tmax = ckey + 2;                                     // [b]: maximum over the touched groups
+  int* rowq = reinterpret_cast<int*>(tmax + 2);                  // row-batch counter
 
   // ---- per-signal constants, group maxima, scratch reset ----
   for (int t = threadIdx.x; t < W * W; t += NT) {
@@ -1491,6 +1512,10 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     if (lane == 0) gkey[g] = wm;
   }
   for (int i = threadIdx.x; i < NPRE * GL; i += NT) scratch[i] = KEY_SENT;
+  if (threadIdx.x < 4) ckey[threadIdx.x] = 0ull;  // ckey[0..1], tmax[0..1]
+  static_assert(2 * NW <= 16, "owner slots");
+  static_assert(2 * NW <= 16, "owner slots");
+  if (threadIdx.x == 0) *rowq = 0;
   __syncthreads();
 
   SigState st = A.state[s];
@@ -1508,193 +1533,353 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   int stop = 0;
   int64_t c_upd = 0, c_blk = 0, c_grp = 0;
 
+  // Wave 0: maximum group key.
+  auto scan_root = [&]() -> uint64_t {
+    uint64_t best = 0ull;
+    for (int i0 = 0; i0 < ngp; i0 += 512) {
+      const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(gkey + i0);
+      const ulonglong2 a = g2[lane], b = g2[lane + 64], c = g2[lane + 128], d = g2[lane + 192];
+      best = umax64(best, umax64(umax64(umax64(a.x, a.y), umax64(b.x, b.y)),
+                                 umax64(umax64(c.x, c.y), umax64(d.x, d.y))));
+    }
+    return wave_max_key2<float>(best);
+  };
+
+  // Wave 0: decode key bk (the selected atom), lay out its target grids and
+  // compute its adjusted coefficient into buffer b.  Reads rho(p): the caller
+  // guarantees that no row being updated covers p.
+  auto select_into = [&](uint64_t bk, int b) {
+    It32* itb = it2 + b;
+    RowT* tgb = tg2 + b * MAXW;
+    if ((uint32_t)(bk >> 32) == 0u) {  // max score is zero
+      if (lane == 0) itb->stop = 1;
+      return;
+    }
+    const int p = uni_i((int)~(uint32_t)bk);
+    const int v = uni_i(__popcll(__ballot(lane < W && p >= d_off)) - 1);
+    const int off_v = (int)rdlane32((uint32_t)d_off, v), MR_v = (int)rdlane32((uint32_t)d_MR, v);
+    const int M_v = (int)rdlane32((uint32_t)d_M, v), sh_v = (int)rdlane32((uint32_t)d_sh, v);
+    const uint32_t mul_v = rdlane32(d_mul, v);
+    const int q0 = p - off_v;
+    const int j = magic_div(q0, mul_v, sh_v);
+    const int kk = q0 - j * MR_v;
+    const bool pair = kk != 0 && 2 * kk != M_v;
+    const int vmask = M_v - 1;
+    const Cx<float> rp = rho[p];
+    const Cx<float> gam = gams[(int)rdlane32((uint32_t)d_gam, v) + (pair ? kk : 0)];
+
+    // geometry of target u = lane (all lanes compute; lanes >= W are discarded)
+    const int u = lane < W ? lane : 0;
+    const PairC P = pc[u * W + v];
+    RowT T;
+    T.MR = P.MR; T.N = P.N; T.off = P.off; T.lbase = P.lbase; T.lpf = P.lpf;
+    const int kr = kk * P.rv;
+    T.rsh = P.rw_sh;
+    T.mm = P.Mmax - 1;
+    T.k1 = kr + P.mulo;
+    T.k2 = P.mulo - kr;
+    T.mspan = P.muhi - P.mulo;
+    T.pad[0] = d_gam;  // gamma(m) of target u's bins (lane u holds system u's offset)
+    T.pad[1] = T.pad[2] = 0;
+    const int jsv = j * P.sv;
+    const int nlo = -((P.dbox - jsv) >> P.sw_sh), nhi = (jsv + P.dbox) >> P.sw_sh;
+    const int half = P.M >> 1;
+    // bins m in [0, M/2] with m r_w in +-k r_v + [mu_lo, mu_hi] (mod M_max)
+    int mlo = 1 << 30, mhi = -1;
+#pragma unroll
+    for (int term = 0; term < 2; ++term) {
+      const int base = term == 0 ? kr : -kr;
+      const int A1 = -((-(base + P.mulo)) >> P.rw_sh), B1 = (base + P.muhi) >> P.rw_sh;
+      const bool use = term == 0 || pair;
+      const bool full = B1 - A1 + 1 >= P.M;
+#pragma unroll
+      for (int c = -1; c <= 1; ++c) {
+        const int lo = full ? 0 : max(A1 + c * P.M, 0), hi = full ? half : min(B1 + c * P.M, half);
+        const bool ok = use && lo <= hi;
+        mlo = ok ? min(mlo, lo) : mlo;
+        mhi = ok ? max(mhi, hi) : mhi;
+      }
+    }
+    const bool valid = lane < W && P.dbox >= 0 && mhi >= 0 && nhi >= nlo;
+    const int nl = nlo < 0 ? nlo + P.N : (nlo >= P.N ? nlo - P.N : nlo);
+    T.nlo = nl;
+    T.nF = valid ? nhi - nlo + 1 : 0;
+    const int dlo = nlo * P.sw - jsv;  // delta of the first frame, in [-dbox, dbox]
+    T.ilo = valid ? mlo >> LOG_ROW : 0;
+    T.bpf = valid ? (mhi >> LOG_ROW) - T.ilo + 1 : 1;
+    T.rbpf = 1.0f / (float)T.bpf;
+    T.hrow0 = (int)P.tab + (dlo + P.dbox) * P.width;
+    T.hstep = P.width * P.sw;
+    const uint32_t cph = (uint32_t)(kk * P.amin) & (uint32_t)vmask;
+    T.ph0 = (uint32_t)dlo * cph;
+    T.phs = cph * (uint32_t)P.sw;
+    const int t_items = valid ? ((T.nF * T.bpf) + 7) & ~7 : 0;  // whole 8-row slots per target
+    const int ihi = mhi >> LOG_ROW;
+    const int nend = T.nlo + T.nF - 1;
+    const int nAe = min(nend, T.N - 1);
+    T.gA_lo = (T.lbase + T.nlo * T.lpf + T.ilo) >> LOG_GL;
+    T.gA_n = valid ? ((T.lbase + nAe * T.lpf + ihi) >> LOG_GL) - T.gA_lo + 1 : 0;
+    T.gB_lo = (T.lbase + T.ilo) >> LOG_GL;
+    const int gBhi = min((T.lbase + (nend - T.N) * T.lpf + ihi) >> LOG_GL, T.gA_lo - 1);
+    T.gB_n = (valid && nend >= T.N) ? max(0, gBhi - T.gB_lo + 1) : 0;
+    const int t_groups = T.gA_n + T.gB_n;
+    int ib = 0, sb = 0;
+    for (int w = 0; w + 1 < W; ++w) {
+      const int iw = (int)rdlane32((uint32_t)t_items, w), gw = (int)rdlane32((uint32_t)t_groups, w);
+      ib += w < lane ? iw : 0;
+      sb += w < lane ? gw : 0;
+    }
+    T.item_base = ib;
+    T.slot_base = sb;
+    // cross-lane reads with the whole wave active
+    const int T_items = (int)rdlane32((uint32_t)(ib + t_items), W - 1);
+    const int TG = (int)rdlane32((uint32_t)(sb + t_groups), W - 1);
+    const int root_v = (int)rdlane32((uint32_t)d_root, v);
+    if (lane < W) {
+      tgb[lane] = T;
+      itb->ibase[lane] = ib;
+      itb->sbase[lane] = sb;
+    }
+    // group of touched-group slot gs = lane
+    {
+      int alo = 0, an = 0, blo = 0, sbw = 0;
+      for (int w = 0; w < W; ++w) {
+        const int s_b = (int)rdlane32((uint32_t)sb, w);
+        const int a_lo = (int)rdlane32((uint32_t)T.gA_lo, w), a_n = (int)rdlane32((uint32_t)T.gA_n, w);
+        const int b_lo = (int)rdlane32((uint32_t)T.gB_lo, w);
+        const bool mine = s_b <= lane;  // the last target starting at or before slot lane
+        alo = mine ? a_lo : alo;
+        an = mine ? a_n : an;
+        blo = mine ? b_lo : blo;
+        sbw = mine ? s_b : sbw;
+      }
+      const int c = lane - sbw;
+      const int g = c < an ? alo + c : blo + (c - an);
+      if (lane < NPRE) itb->gown[lane] = lane < TG ? g : 0;
+    }
+    // coefficient adjustment for the pair, Eq. (dualatprod), and energy
+    // decrease, Eq. (projenfaster)
+    Cx<float> cc;
+    double Et;
+    bool partner = false;
+    {
+      const float rr = rp.re, ri = rp.im;
+      if (pair) {
+        const float gr = gam.re, gi = gam.im;
+        const float nr = rr - (gr * rr - gi * ri);
+        const float ni = ri - (-gr * ri - gi * rr);
+        const float den = 1.0f - (gr * gr + gi * gi);
+        cc.re = nr / den;
+        cc.im = ni / den;
+        const double cr = cc.re, ci = cc.im, dgr = gr, dgi = gi;
+        Et = 2.0 * (cr * cr + ci * ci + dgr * (cr * cr - ci * ci) - 2.0 * dgi * cr * ci);
+        partner = A.partner_gate ? (gr != 0.0f || gi != 0.0f) : true;
+      } else {
+        cc.re = rr;
+        cc.im = ri;
+        const double cr = cc.re, ci = cc.im;
+        Et = cr * cr + ci * ci;
+      }
+    }
+    if (lane == 0) {
+      int4* I = reinterpret_cast<int4*>(&itb->p);
+      I[0] = make_int4(p, v, kk, j);
+      I[1] = make_int4(pair, T_items, TG, 0);
+      I[2] = make_int4(root_v, vmask, partner, 0);
+      itb->cc = cc;
+      itb->Et = Et;
+    }
+  };
+
+  // per-selection values every wave reads from buffer b (one batch of LDS reads)
+  struct ItR {
+    int4 I0, I1, I2;
+    Cx<float> cc;
+    double Et;
+    int ibase, sbase, g0, g1;
+  };
+  auto read_it = [&](int b) -> ItR {
+    const It32* itb = it2 + b;
+    ItR r;
+    r.I0 = *reinterpret_cast<const int4*>(&itb->p);
+    r.I1 = *reinterpret_cast<const int4*>(&itb->pair);
+    r.I2 = *reinterpret_cast<const int4*>(&itb->root_off);
+    r.cc = itb->cc;
+    r.Et = itb->Et;
+    r.ibase = lane < W ? itb->ibase[lane] : 0x7fffffff;
+    r.sbase = lane < W ? itb->sbase[lane] : 0x7fffffff;
+    r.g0 = itb->gown[wave];
+    r.g1 = itb->gown[wave + NW];
+    return r;
+  };
+
+  // ---- rows of one batch: loads, update, new leaves ----
+  // A slot is 8 rows; 8 lanes per row, each with 2 adjacent bins m0 = 16 i +
+  // 2 rl8 and m0 + 1.  fl bit 0: row in grid, 1/2: bin 0/1 valid, 3/4: term 1
+  // of bin 0/1 in the box, 5/6: term 2 of bin 0/1, 7: pedantic score.
+  auto do_batch = [&](const RowT* tg, int qb, int nact, int ibase, int p, bool pair, bool partner,
+                      uint32_t root_off, uint32_t vmask, Cx<float> cc) {
+    C4f r[SLOTS], gg[SLOTS];
+    Cx<float> h1a[SLOTS], h1b[SLOTS], h2a[SLOTS], h2b[SLOTS], ph[SLOTS];
+    uint32_t ee[SLOTS], lfi[SLOTS], fl[SLOTS];
+    int gsl[SLOTS];
+    {
+      int cw = -1;
+      RowT T;
+#pragma unroll
+      for (int sl = 0; sl < SLOTS; ++sl) {
+        if (sl >= nact) break;  // wave-uniform
+        const int base8 = (qb + sl) * 8;
+        const int w = uni_i(__popcll(__ballot(ibase <= base8)) - 1);
+        if (w != cw) {
+          T = tg[w];
+          cw = w;
+        }
+        // row t of target w's grid: frame f, 16-bin block i
+        const int t = base8 - T.item_base + rid8;
+        int f = (int)((float)t * T.rbpf);
+        f -= f * T.bpf > t ? 1 : 0;
+        f += (f + 1) * T.bpf <= t ? 1 : 0;
+        const int i = T.ilo + t - f * T.bpf;
+        const bool ok = f < T.nF;
+        int n = T.nlo + f;
+        n -= n >= T.N ? T.N : 0;
+        const int li = T.lbase + n * T.lpf + i;
+        const int m0 = (i << LOG_ROW) + 2 * rl8;
+        const bool v0 = ok && m0 < T.MR, v1 = ok && m0 + 1 < T.MR;
+        const uint32_t e = (uint32_t)(T.off + n * T.MR + m0);
+        const uint32_t hrow = (uint32_t)(T.hrow0 + f * T.hstep);
+        const uint32_t mm = (uint32_t)T.mm, step = 1u << T.rsh;
+        const uint32_t u1 = (uint32_t)((m0 << T.rsh) - T.k1) & mm, u1b = (u1 + step) & mm;
+        const uint32_t u2 = (uint32_t)((m0 << T.rsh) - T.k2) & mm, u2b = (u2 + step) & mm;
+        const uint32_t span = (uint32_t)T.mspan;
+        const bool i1a = v0 && u1 <= span, i1b = v1 && u1b <= span;
+        const bool i2a = v0 && pair && u2 <= span, i2b = v1 && pair && u2b <= span;
+        // every lane loads (out-of-grid lanes from valid stand-in addresses;
+        // the second bin of a pair may lie one element past its frame)
+        r[sl] = ld_c4(rho + (v0 ? e : (uint32_t)p));
+        h1a[sl] = tabs[i1a ? hrow + u1 : 0u];
+        h1b[sl] = tabs[i1b ? hrow + u1b : 0u];
+        h2a[sl] = tabs[i2a ? hrow + u2 : 0u];
+        h2b[sl] = tabs[i2b ? hrow + u2b : 0u];
+        ph[sl] = roots[root_off + ((T.ph0 + (uint32_t)f * T.phs) & vmask)];
+        ee[sl] = e;
+        lfi[sl] = (uint32_t)li;
+        gg[sl] = C4f{0.0f, 0.0f, 0.0f, 0.0f};
+        if (pedantic) gg[sl] = ld_c4(gams + (v0 ? (uint32_t)(T.pad[0] + m0) : 0u));
+        // the pedantic score applies to bins with a partner (not DC, not Nyquist)
+        const bool pe0 = pedantic && m0 != 0 && m0 != T.MR - 1, pe1 = pedantic && m0 + 1 != T.MR - 1;
+        fl[sl] = (ok ? 1u : 0u) | (v0 ? 2u : 0u) | (v1 ? 4u : 0u) | (i1a ? 8u : 0u) | (i1b ? 16u : 0u) |
+                 (i2a ? 32u : 0u) | (i2b ? 64u : 0u) | (pe0 ? 128u : 0u) | (pe1 ? 256u : 0u);
+        // touched-group slot of the row's group
+        const int g = li >> LOG_GL;
+        gsl[sl] = T.slot_base + ((g >= T.gA_lo && g < T.gA_lo + T.gA_n) ? g - T.gA_lo : T.gA_n + g - T.gB_lo);
+      }
+    }
+    uint32_t n_upd = 0, n_blk = 0;
+#pragma unroll
+    for (int sl = 0; sl < SLOTS; ++sl) {
+      if (sl >= nact) break;  // wave-uniform
+      const uint32_t fs = fl[sl];
+      const float cs = ph[sl].re, sn = ph[sl].im;
+      // c (h1 phi) + conj(c) (h2 conj(phi)) for one bin
+      auto upd = [&](Cx<float> a1, Cx<float> b2, float& re, float& im) {
+        const float ar = a1.re * cs - a1.im * sn, ai = a1.re * sn + a1.im * cs;
+        float ur = cc.re * ar - cc.im * ai, ui = cc.re * ai + cc.im * ar;
+        const float br = b2.re * cs + b2.im * sn, bi = b2.im * cs - b2.re * sn;
+        ur += cc.re * br + cc.im * bi;
+        ui += cc.re * bi - cc.im * br;
+        re -= ur;
+        im -= ui;
+      };
+      const Cx<float> z{0.0f, 0.0f};
+      const Cx<float> a1 = (fs & 8u) ? h1a[sl] : z, a2 = (fs & 16u) ? h1b[sl] : z;
+      const Cx<float> b1 = ((fs & 32u) && partner) ? h2a[sl] : z, b2 = ((fs & 64u) && partner) ? h2b[sl] : z;
+      const bool nz0 = (a1.re != 0.0f) | (a1.im != 0.0f) | (b1.re != 0.0f) | (b1.im != 0.0f);
+      const bool nz1 = (a2.re != 0.0f) | (a2.im != 0.0f) | (b2.re != 0.0f) | (b2.im != 0.0f);
+      C4f rv = r[sl];
+      upd(a1, b1, rv.x, rv.y);
+      upd(a2, b2, rv.z, rv.w);
+      if (nz0 | nz1) {
+        if (fs & 4u)
+          st_c4(rho + ee[sl], rv);
+        else
+          rho[ee[sl]] = Cx<float>{rv.x, rv.y};
+      }
+      const float s0 = sel_score<float>(rv.x, rv.y, Cx<float>{gg[sl].x, gg[sl].y}, (fs & 128u) != 0);
+      const float s1 = sel_score<float>(rv.z, rv.w, Cx<float>{gg[sl].z, gg[sl].w}, (fs & 256u) != 0);
+      const uint32_t bits0 = (fs & 2u) ? __float_as_uint(s0) : 0u;
+      const uint32_t bits1 = (fs & 4u) ? __float_as_uint(s1) : 0u;
+      uint32_t rm = bits0 > bits1 ? bits0 : bits1;
+      rm = max_dpp32<0xB1>(rm);
+      rm = max_dpp32<0x4E>(rm);
+      rm = max_dpp32<0x141>(rm);  // half-row mirror: the two quads of an 8-lane row
+      const bool hit0 = (fs & 2u) && bits0 == rm, hit1 = (fs & 4u) && bits1 == rm;
+      const uint64_t bal = __ballot(hit0 | hit1);
+      const uint32_t rowbits = (uint32_t)(bal >> (rid8 * 8)) & 0xFFu;
+      const bool leader = (fs & 1u) && rowbits && lane == rid8 * 8 + __ffs(rowbits) - 1;
+      n_upd += (uint32_t)(__popcll(__ballot(nz0)) + __popcll(__ballot(nz1)));
+      n_blk += (uint32_t)__popcll(__ballot(leader));
+      if (leader) {
+        const uint32_t eb = ee[sl] + (hit0 ? 0u : 1u);  // lowest bin holding the row maximum
+        const uint64_t key = ((uint64_t)rm << 32) | (uint64_t)(~eb);
+        const uint32_t b = lfi[sl];
+        leaves[b] = key;
+        if (gsl[sl] < NPRE) scratch[gsl[sl] * GL + (b & (GL - 1))] = key;
+      }
+    }
+    c_upd += n_upd;
+    c_blk += n_blk;
+  };
+  // wave: next batch index from the shared counter
+  auto grab = [&]() -> int {
+    int qi = 0;
+    if (lane == 0) qi = atomicAdd(rowq, 1);
+    return uni_i(qi);
+  };
+
+  // first selection: full scan
+  int cur = 0;
+  if (wave == 0) select_into(scan_root(), 0);
+  __syncthreads();
+  ItR cr = read_it(0);
+
   for (;;) {
     if (k >= K) { stop = 1; break; }
     if (E <= Etarget) { stop = 2; break; }
     if (E < 0.0) { stop = 3; break; }
-
-    // ---- wave 0: root, decode, target grids, adjustment ----
-    if (wave == 0) {
-      uint64_t best = 0ull;
-      for (int i0 = 0; i0 < ngp; i0 += 512) {
-        const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(gkey + i0);
-        const ulonglong2 a = g2[lane], b = g2[lane + 64], c = g2[lane + 128], d = g2[lane + 192];
-        best = umax64(best, umax64(umax64(umax64(a.x, a.y), umax64(b.x, b.y)),
-                                   umax64(umax64(c.x, c.y), umax64(d.x, d.y))));
-      }
-      const uint64_t bk = wave_max_key2<float>(best);
-      if ((uint32_t)(bk >> 32) == 0u) {  // max |rho|^2 is zero
-        if (lane == 0) it->stop = 1;
-      } else {
-        const int p = uni_i((int)~(uint32_t)bk);
-        const int v = uni_i(__popcll(__ballot(lane < W && p >= d_off)) - 1);
-        const int off_v = (int)rdlane32((uint32_t)d_off, v), MR_v = (int)rdlane32((uint32_t)d_MR, v);
-        const int M_v = (int)rdlane32((uint32_t)d_M, v), sh_v = (int)rdlane32((uint32_t)d_sh, v);
-        const uint32_t mul_v = rdlane32(d_mul, v);
-        const int q0 = p - off_v;
-        const int j = magic_div(q0, mul_v, sh_v);
-        const int kk = q0 - j * MR_v;
-        const bool pair = kk != 0 && 2 * kk != M_v;
-        const int vmask = M_v - 1;
-        // rho(p) and gamma, consumed at the end of this phase (no row is
-        // rewritten before the barrier)
-        const Cx<float> rp = rho[p];
-        const Cx<float> gam = gams[(int)rdlane32((uint32_t)d_gam, v) + (pair ? kk : 0)];
-
-        // geometry of target u = lane (all lanes compute; lanes >= W are discarded)
-        const int u = lane < W ? lane : 0;
-        const PairC P = pc[u * W + v];
-        RowT T;
-        T.MR = P.MR; T.N = P.N; T.off = P.off; T.lbase = P.lbase; T.lpf = P.lpf;
-        const int kr = kk * P.rv;
-        T.rsh = P.rw_sh;
-        T.mm = P.Mmax - 1;
-        T.k1 = kr + P.mulo;
-        T.k2 = P.mulo - kr;
-        T.mspan = P.muhi - P.mulo;
-        T.pad[0] = d_gam;  // gamma(m) of target u's bins (lane u holds system u's offset)
-        T.pad[1] = T.pad[2] = 0;
-        const int jsv = j * P.sv;
-        const int nlo = -((P.dbox - jsv) >> P.sw_sh), nhi = (jsv + P.dbox) >> P.sw_sh;
-        const int half = P.M >> 1;
-        // bins m in [0, M/2] with m r_w in +-k r_v + [mu_lo, mu_hi] (mod M_max)
-        int mlo = 1 << 30, mhi = -1;
-#pragma unroll
-        for (int term = 0; term < 2; ++term) {
-          const int base = term == 0 ? kr : -kr;
-          const int A1 = -((-(base + P.mulo)) >> P.rw_sh), B1 = (base + P.muhi) >> P.rw_sh;
-          const bool use = term == 0 || pair;
-          const bool full = B1 - A1 + 1 >= P.M;
-#pragma unroll
-          for (int c = -1; c <= 1; ++c) {
-            const int lo = full ? 0 : max(A1 + c * P.M, 0), hi = full ? half : min(B1 + c * P.M, half);
-            const bool ok = use && lo <= hi;
-            mlo = ok ? min(mlo, lo) : mlo;
-            mhi = ok ? max(mhi, hi) : mhi;
-          }
-        }
-        const bool valid = lane < W && P.dbox >= 0 && mhi >= 0 && nhi >= nlo;
-        const int nl = nlo < 0 ? nlo + P.N : (nlo >= P.N ? nlo - P.N : nlo);
-        T.nlo = nl;
-        T.nF = valid ? nhi - nlo + 1 : 0;
-        const int dlo = nlo * P.sw - jsv;  // delta of the first frame, in [-dbox, dbox]
-        T.ilo = valid ? mlo >> LOG_ROW : 0;
-        T.bpf = valid ? (mhi >> LOG_ROW) - T.ilo + 1 : 1;
-        T.rbpf = 1.0f / (float)T.bpf;
-        T.hrow0 = (int)P.tab + (dlo + P.dbox) * P.width;
-        T.hstep = P.width * P.sw;
-        const uint32_t cph = (uint32_t)(kk * P.amin) & (uint32_t)vmask;
-        T.ph0 = (uint32_t)dlo * cph;
-        T.phs = cph * (uint32_t)P.sw;
-        const int t_items = valid ? ((T.nF * T.bpf) + 3) & ~3 : 0;
-        const int ihi = mhi >> LOG_ROW;
-        const int nend = T.nlo + T.nF - 1;
-        const int nAe = min(nend, T.N - 1);
-        T.gA_lo = (T.lbase + T.nlo * T.lpf + T.ilo) >> LOG_GL;
-        T.gA_n = valid ? ((T.lbase + nAe * T.lpf + ihi) >> LOG_GL) - T.gA_lo + 1 : 0;
-        T.gB_lo = (T.lbase + T.ilo) >> LOG_GL;
-        const int gBhi = min((T.lbase + (nend - T.N) * T.lpf + ihi) >> LOG_GL, T.gA_lo - 1);
-        T.gB_n = (valid && nend >= T.N) ? max(0, gBhi - T.gB_lo + 1) : 0;
-        const int t_groups = T.gA_n + T.gB_n;
-        int ib = 0, sb = 0;
-        for (int w = 0; w + 1 < W; ++w) {
-          const int iw = (int)rdlane32((uint32_t)t_items, w), gw = (int)rdlane32((uint32_t)t_groups, w);
-          ib += w < lane ? iw : 0;
-          sb += w < lane ? gw : 0;
-        }
-        T.item_base = ib;
-        T.slot_base = sb;
-        // cross-lane reads with the whole wave active
-        const int T_items = (int)rdlane32((uint32_t)(ib + t_items), W - 1);
-        const int TG = (int)rdlane32((uint32_t)(sb + t_groups), W - 1);
-        const int root_v = (int)rdlane32((uint32_t)d_root, v);
-        if (lane < W) {
-          tg[lane] = T;
-          it->ibase[lane] = ib;
-          it->sbase[lane] = sb;
-        }
-        // coefficient adjustment for the pair, Eq. (dualatprod), and energy
-        // decrease, Eq. (projenfaster)
-        Cx<float> cc;
-        double Et;
-        bool partner = false;
-        {
-          const float rr = rp.re, ri = rp.im;
-          if (pair) {
-            const float gr = gam.re, gi = gam.im;
-            const float nr = rr - (gr * rr - gi * ri);
-            const float ni = ri - (-gr * ri - gi * rr);
-            const float den = 1.0f - (gr * gr + gi * gi);
-            cc.re = nr / den;
-            cc.im = ni / den;
-            const double cr = cc.re, ci = cc.im, dgr = gr, dgi = gi;
-            Et = 2.0 * (cr * cr + ci * ci + dgr * (cr * cr - ci * ci) - 2.0 * dgi * cr * ci);
-            partner = A.partner_gate ? (gr != 0.0f || gi != 0.0f) : true;
-          } else {
-            cc.re = rr;
-            cc.im = ri;
-            const double cr = cc.re, ci = cc.im;
-            Et = cr * cr + ci * ci;
-          }
-        }
-        if (lane == 0) {
-          int4* I = reinterpret_cast<int4*>(&it->p);
-          I[0] = make_int4(p, v, kk, j);
-          I[1] = make_int4(pair, T_items, TG, 0);
-          I[2] = make_int4(root_v, vmask, partner, 0);
-          it->cc = cc;
-          it->Et = Et;
-          AtomRec ar;
-          ar.w = v;
-          ar.m = kk;
-          ar.n = j;
-          ar.pad = 0;
-          ar.re = (double)cc.re;
-          ar.im = (double)cc.im;
-          ar.E_after = E - Et;
-          A.atoms[S.atom_base + k] = ar;
-        }
-      }
+    if (uni_i(cr.I1.w)) {  // max score is zero
+      stop = 4;
+      break;
     }
-    __syncthreads();
-    {
-      const int istop = uni_i(it->stop);
-      if (istop) {
-        stop = 4;
-        break;
-      }
+    const RowT* tg = tg2 + cur * MAXW;
+    const int p = uni_i(cr.I0.x);
+    const bool pair = uni_i(cr.I1.x) != 0;
+    const int T_items = uni_i(cr.I1.y), TG = uni_i(cr.I1.z);
+    const uint32_t root_off = (uint32_t)uni_i(cr.I2.x);
+    const uint32_t vmask = (uint32_t)uni_i(cr.I2.y);
+    const bool partner = uni_i(cr.I2.z) != 0;
+    const int ibase = cr.ibase, sbase = cr.sbase;
+    const Cx<float> cc = cr.cc;
+    const double Et = cr.Et;
+    if (wave == 0 && lane == 0) {
+      AtomRec ar;
+      ar.w = cr.I0.y;
+      ar.m = cr.I0.z;
+      ar.n = cr.I0.w;
+      ar.pad = 0;
+      ar.re = (double)cc.re;
+      ar.im = (double)cc.im;
+      ar.E_after = E - Et;
+      A.atoms[S.atom_base + k] = ar;
     }
-    const int4 I0 = *reinterpret_cast<const int4*>(&it->p);
-    const int4 I1 = *reinterpret_cast<const int4*>(&it->pair);
-    const int4 I2 = *reinterpret_cast<const int4*>(&it->root_off);
-    const Cx<float> cc = it->cc;
-    const double Et = it->Et;
-    const int ibase = lane < W ? it->ibase[lane] : 0x7fffffff;
-    const int sbase = lane < W ? it->sbase[lane] : 0x7fffffff;
-    const int p = uni_i(I0.x);
-    const bool pair = uni_i(I1.x) != 0;
-    const int T_items = uni_i(I1.y), TG = uni_i(I1.z);
-    const uint32_t root_off = (uint32_t)uni_i(I2.x);
-    const uint32_t vmask = (uint32_t)uni_i(I2.y);
-    const bool partner = uni_i(I2.z) != 0;
     E -= Et;
     ++k;
 
-    // touched-group slots this wave merges: gs = wave and wave + NW
+    // touched-group slots this wave merges: gs = wave and wave + NW; their
+    // old leaves are loaded now and consumed after the update
     const int gs0 = wave, gs1 = wave + NW;
-    int g0 = 0, g1 = 0;
-    {
-      const int w0 = uni_i(__popcll(__ballot(sbase <= gs0)) - 1);
-      const int w1 = uni_i(__popcll(__ballot(sbase <= gs1)) - 1);
-      const int4 a0 = *reinterpret_cast<const int4*>(&tg[w0].gA_lo);
-      const int sb0 = tg[w0].slot_base;
-      const int4 a1 = *reinterpret_cast<const int4*>(&tg[w1].gA_lo);
-      const int sb1 = tg[w1].slot_base;
-      const int c0 = gs0 - sb0, c1 = gs1 - sb1;
-      g0 = uni_i(c0 < a0.y ? a0.x + c0 : a0.z + (c0 - a0.y));
-      g1 = uni_i(c1 < a1.y ? a1.x + c1 : a1.z + (c1 - a1.y));
-    }
-    // preload their old leaves
+    const int g0 = uni_i(cr.g0), g1 = uni_i(cr.g1);
     uint64_t old0[LPL], old1[LPL];
     if (gs0 < TG) {
 #pragma unroll
@@ -1705,128 +1890,70 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       for (int x = 0; x < LPL; ++x) old1[x] = leaves[(uint32_t)(g1 * GL + lane + 64 * x)];
     }
 
-    // ---- rows of the target grids: loads, update, new leaves ----
-    const int nslots = T_items >> 2;
-    const int chunk = (nslots + NW - 1) / NW;
-    const int q_begin = wave * chunk, q_end = min(nslots, q_begin + chunk);
-    for (int qb = q_begin; qb < q_end; qb += SLOTS) {
-      const int nact = min(SLOTS, q_end - qb);
-      Cx<float> r[SLOTS], h1[SLOTS], h2[SLOTS], ph[SLOTS], gg[SLOTS];
-      // fl bit 0: row in grid, 1: bin valid, 2/3: term 1/2 in box, 4: pedantic score
-      uint32_t ee[SLOTS], lfi[SLOTS], fl[SLOTS];
-      int gsl[SLOTS];
-      {
-        int cw = -1;
-        RowT T;
-#pragma unroll
-        for (int sl = 0; sl < SLOTS; ++sl) {
-          if (sl >= nact) break;  // wave-uniform
-          const int base4 = (qb + sl) * 4;
-          const int w = uni_i(__popcll(__ballot(ibase <= base4)) - 1);
-          if (w != cw) {
-            T = tg[w];
-            cw = w;
-          }
-          // row t of target w's grid: frame f, 16-bin block i
-          const int t = base4 - T.item_base + rid;
-          int f = (int)((float)t * T.rbpf);
-          f -= f * T.bpf > t ? 1 : 0;
-          f += (f + 1) * T.bpf <= t ? 1 : 0;
-          const int i = T.ilo + t - f * T.bpf;
-          const bool ok = f < T.nF;
-          int n = T.nlo + f;
-          n -= n >= T.N ? T.N : 0;
-          const int li = T.lbase + n * T.lpf + i;
-          const int m = (i << LOG_ROW) + rl;
-          const bool vl = ok && m < T.MR;
-          const uint32_t e = (uint32_t)(T.off + n * T.MR + m);
-          const uint32_t hrow = (uint32_t)(T.hrow0 + f * T.hstep);
-          const uint32_t u1 = (uint32_t)((m << T.rsh) - T.k1) & (uint32_t)T.mm;
-          const uint32_t u2 = (uint32_t)((m << T.rsh) - T.k2) & (uint32_t)T.mm;
-          const bool in1 = vl && u1 <= (uint32_t)T.mspan;
-          const bool in2 = vl && pair && u2 <= (uint32_t)T.mspan;
-          // every lane loads (out-of-grid lanes from valid stand-in addresses)
-          r[sl] = rho[vl ? e : (uint32_t)p];
-          h1[sl] = tabs[in1 ? hrow + u1 : 0u];
-          h2[sl] = tabs[in2 ? hrow + u2 : 0u];
-          ph[sl] = roots[root_off + ((T.ph0 + (uint32_t)f * T.phs) & vmask)];
-          ee[sl] = e;
-          lfi[sl] = (uint32_t)li;
-          const bool pb = pedantic && vl && m != 0 && m != T.MR - 1;
-          gg[sl] = Cx<float>{0.0f, 0.0f};
-          if (pedantic) gg[sl] = gams[pb ? (uint32_t)(T.pad[0] + m) : 0u];
-          fl[sl] = (ok ? 1u : 0u) | (vl ? 2u : 0u) | (in1 ? 4u : 0u) | (in2 ? 8u : 0u) | (pb ? 16u : 0u);
-          // touched-group slot of the row's group
-          const int g = li >> LOG_GL;
-          gsl[sl] = T.slot_base + ((g >= T.gA_lo && g < T.gA_lo + T.gA_n) ? g - T.gA_lo : T.gA_n + g - T.gB_lo);
-        }
+    // ---- wave 0: candidate for the next selection ----
+    // The touched groups' keys are cleared (the merge below rewrites them);
+    // the maximum over the others cannot change in this update, so it is the
+    // next selection unless a touched group ends above it.
+    if (wave == 0) {
+      for (int w = 0; w < W; ++w) {
+        const int4 a = *reinterpret_cast<const int4*>(&tg[w].gA_lo);
+        const int alo = uni_i(a.x), an = uni_i(a.y), blo = uni_i(a.z), bn = uni_i(a.w);
+        for (int i = lane; i < an; i += 64) gkey[alo + i] = 0ull;
+        for (int i = lane; i < bn; i += 64) gkey[blo + i] = 0ull;
       }
-#pragma unroll
-      for (int sl = 0; sl < SLOTS; ++sl) {
-        if (sl >= nact) break;  // wave-uniform
-        const uint32_t fs = fl[sl];
-        const Cx<float> a1 = (fs & 4u) ? h1[sl] : Cx<float>{0.0f, 0.0f};
-        const Cx<float> b2 = ((fs & 8u) && partner) ? h2[sl] : Cx<float>{0.0f, 0.0f};
-        const bool nz = (a1.re != 0.0f) | (a1.im != 0.0f) | (b2.re != 0.0f) | (b2.im != 0.0f);
-        const float cs = ph[sl].re, sn = ph[sl].im;
-        // c (h1 phi) + conj(c) (h2 conj(phi))
-        const float ar = a1.re * cs - a1.im * sn, ai = a1.re * sn + a1.im * cs;
-        float ur = cc.re * ar - cc.im * ai, ui = cc.re * ai + cc.im * ar;
-        const float br = b2.re * cs + b2.im * sn, bi = b2.im * cs - b2.re * sn;
-        ur += cc.re * br + cc.im * bi;
-        ui += cc.re * bi - cc.im * br;
-        Cx<float> rv = r[sl];
-        rv.re -= ur;
-        rv.im -= ui;
-        if (nz) rho[ee[sl]] = rv;
-        const bool vl = (fs & 2u) != 0;
-        const float val = sel_score<float>(rv.re, rv.im, gg[sl], (fs & 16u) != 0);
-        const uint32_t bits = vl ? __float_as_uint(val) : 0u;
-        const uint32_t rm = (uint32_t)row_max_bits<float>(bits);
-        const uint64_t bal = __ballot(vl && bits == rm);
-        const uint32_t rowbits = (uint32_t)(bal >> (rid * ROW)) & 0xFFFFu;
-        const bool leader = (fs & 1u) && rowbits && lane == rid * ROW + __ffs(rowbits) - 1;
-        c_upd += __popcll(__ballot(nz));
-        c_blk += __popcll(__ballot(leader));
-        if (leader) {
-          const uint64_t key = ((uint64_t)bits << 32) | (uint64_t)(~ee[sl]);
-          const uint32_t b = lfi[sl];
-          leaves[b] = key;
-          if (gsl[sl] < NPRE) scratch[gsl[sl] * GL + (b & (GL - 1))] = key;
+      const uint64_t bk = scan_root();
+      select_into(bk, cur ^ 1);
+      if (lane == 0) ckey[cur ^ 1] = bk;
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): no load of this block stays in flight into the rows
+    }
+
+    // ---- rows: batches of bs slots (8 rows each) from a shared counter,
+    // sized so that waves 1..NW-1 take one batch each; wave 0 joins once its
+    // candidate is built.  The first batch is peeled: waiting for its loads
+    // also completes the old-leaf loads above, so the merge does not wait on
+    // this wave's row stores.
+    {
+      const int nslots = T_items >> 3;
+      const int bs = min(SLOTS, max(1, (nslots + NW - 2) / (NW - 1)));
+      int qb = grab() * bs;
+      if (qb < nslots) {
+        do_batch(tg, qb, min(bs, nslots - qb), ibase, p, pair, partner, root_off, vmask, cc);
+        for (;;) {
+          qb = grab() * bs;
+          if (qb >= nslots) break;
+          do_batch(tg, qb, min(bs, nslots - qb), ibase, p, pair, partner, root_off, vmask, cc);
         }
+      } else {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       }
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+      *rowq = 0;
+      tmax[cur ^ 1] = 0ull;  // read by every wave after the previous merge, before this barrier
+    }
 
     // ---- touched groups: merge old and rewritten leaves ----
-    if (gs0 < TG) {
+    auto merge_slot = [&](int gs, int g, const uint64_t* old) {
+      uint64_t scv[LPL];
+#pragma unroll
+      for (int x = 0; x < LPL; ++x) scv[x] = scratch[gs * GL + lane + 64 * x];
       uint64_t best = 0ull;
 #pragma unroll
       for (int x = 0; x < LPL; ++x) {
-        uint64_t& sc = scratch[gs0 * GL + lane + 64 * x];
-        const uint64_t scv = sc;
-        const bool w_ = scv != KEY_SENT;
-        if (w_) sc = KEY_SENT;
-        best = umax64(best, w_ ? scv : old0[x]);
+        const bool w_ = scv[x] != KEY_SENT;
+        if (w_) scratch[gs * GL + lane + 64 * x] = KEY_SENT;
+        best = umax64(best, w_ ? scv[x] : old[x]);
       }
       const uint64_t wm = wave_max_key2<float>(best);
-      if (lane == 0) gkey[g0] = wm;
-      ++c_grp;
-    }
-    if (gs1 < TG) {
-      uint64_t best = 0ull;
-#pragma unroll
-      for (int x = 0; x < LPL; ++x) {
-        uint64_t& sc = scratch[gs1 * GL + lane + 64 * x];
-        const uint64_t scv = sc;
-        const bool w_ = scv != KEY_SENT;
-        if (w_) sc = KEY_SENT;
-        best = umax64(best, w_ ? scv : old1[x]);
+      if (lane == 0) {
+        gkey[g] = wm;
+        atomicMax((unsigned long long*)&tmax[cur], (unsigned long long)wm);
       }
-      const uint64_t wm = wave_max_key2<float>(best);
-      if (lane == 0) gkey[g1] = wm;
       ++c_grp;
-    }
+    };
+    if (gs0 < TG) merge_slot(gs0, g0, old0);
+    if (gs1 < TG) merge_slot(gs1, g1, old1);
     // slots beyond the preloaded ones: the leaves in global memory are current
     for (int gs = NPRE + wave; gs < TG; gs += NW) {
       const int w = uni_i(__popcll(__ballot(sbase <= gs)) - 1);
@@ -1837,10 +1964,23 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
 #pragma unroll
       for (int x = 0; x < LPL; ++x) best = umax64(best, leaves[(uint32_t)(g * GL + lane + 64 * x)]);
       const uint64_t wm = wave_max_key2<float>(best);
-      if (lane == 0) gkey[g] = wm;
+      if (lane == 0) {
+        gkey[g] = wm;
+        atomicMax((unsigned long long*)&tmax[cur], (unsigned long long)wm);
+      }
       ++c_grp;
     }
     __syncthreads();
+
+    // the candidate stands unless a touched group now holds a larger key
+    const uint64_t kc = ckey[cur ^ 1], kt = tmax[cur];
+    cur ^= 1;
+    cr = read_it(cur);
+    if (kc < kt) {
+      if (wave == 0) select_into(kt, cur);
+      __syncthreads();
+      cr = read_it(cur);
+    }
   }
 
   if (lane == 0) {
@@ -2222,12 +2362,12 @@ hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st
     return launch_mp_t<double, 512, 4>(a, grid, preload, st);
   }
   if (a.G == 128) {
-    if (nt == 256) return launch_mp32_t<256, 6, 128>(a, grid, st);
-    return launch_mp32_t<512, 6, 128>(a, grid, st);
+    if (nt == 256) return launch_mp32_t<256, 4, 128>(a, grid, st);
+    return launch_mp32_t<512, 4, 128>(a, grid, st);
   }
   if (a.G == 256) {
-    if (nt == 256) return launch_mp32_t<256, 6, 256>(a, grid, st);
-    return launch_mp32_t<512, 6, 256>(a, grid, st);
+    if (nt == 256) return launch_mp32_t<256, 4, 256>(a, grid, st);
+    return launch_mp32_t<512, 4, 256>(a, grid, st);
   }
   return hipErrorInvalidValue;
 }
