@@ -243,7 +243,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "mpg::k_mp32<%d, 4, %d>" % (st.threads, st.group_leaves), "alg_bytes_per_launch": alg_bytes,
+                     "kernel": "mpg::k_mp32<%d, 2, %d>" % (st.threads, st.group_leaves), "alg_bytes_per_launch": alg_bytes,
                      "launch_ms": loop_ms},
         "cpu_baseline": cpu,
         "mp_loop_atoms_per_s": loop_rate,

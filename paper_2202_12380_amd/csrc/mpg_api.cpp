@@ -411,6 +411,10 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       for (int w = 0; w < W; ++w) {
         const int MR = dicts[w].M / 2 + 1, lpf = (MR + ROW - 1) / ROW;
         S.N[w] = (int32_t)(S.Lp / dicts[w].a);
+        if (S.N[w] >= (1 << 24)) {  // frame indices enter 24-bit multiplies
+          rc = MP_E_LIMIT;
+          goto fail;
+        }
         S.off[w] = off;
         off += (int64_t)S.N[w] * MR;
         S.lbase[w] = lb;
@@ -540,7 +544,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       ACHK(dalloc(&d_roots, (size_t)Mmax_all));
       ACHK(dalloc(&d_box, 4));
       ACHK(dalloc(&d_max, 1));
-      int64_t tab_total = 0;
+      int64_t tab_total = 0, tab_total32 = 0;
       ptab64.assign((size_t)W * W, nullptr);
       ptab32.assign((size_t)W * W, nullptr);
       for (int w = 0; w < W; ++w)
@@ -585,9 +589,18 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
             P.mu_hi = -1;
           }
           P.width = P.mu_hi - P.mu_lo + 1;
+          P.cw = (P.width + P.rw - 1) / P.rw;
+          P.width32 = P.cw * P.rw;
+          // the FP32 loop steps table rows with 24-bit multiplies
+          if ((int64_t)P.width32 * P.sw >= ((int64_t)1 << 24)) {
+            rc = MP_E_LIMIT;
+            goto fail;
+          }
           const size_t n = P.dbox >= 0 ? (size_t)(2 * P.dbox + 1) * (size_t)P.width : 0;
           P.tab_off = tab_total;
           tab_total += (int64_t)n;
+          P.tab_off32 = tab_total32;
+          tab_total32 += P.dbox >= 0 ? (int64_t)(2 * P.dbox + 1) * P.width32 : 0;
           mp_kernel_info& KI = p->kinfo[idx];
           KI.amin = amin;
           KI.Mmax = Mmax;
@@ -612,14 +625,41 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
             }
           }
         }
+      // rows updated per selection: the FP32 loop maps row -> frame with an
+      // FP32 reciprocal, exact while the row index stays below 2^21
+      for (int v = 0; v < W; ++v) {
+        int64_t rows = 0;
+        for (int w = 0; w < W; ++w) {
+          const PairDev& P = p->hp[w * W + v];
+          if (P.dbox < 0) continue;
+          rows += ((int64_t)2 * P.dbox / P.sw + 10) * (((int64_t)dicts[w].M / 2 + ROW) / ROW);
+        }
+        if (rows >= ((int64_t)1 << 21)) {
+          rc = MP_E_LIMIT;
+          goto fail;
+        }
+      }
       ACHK(dalloc(&p->d_tab64, (size_t)tab_total));
-      ACHK(dalloc(&p->d_tab32, (size_t)tab_total));
+      if (tab_total32 >= ((int64_t)1 << 31)) {  // FP32 table rows are addressed with 32-bit indices
+        rc = MP_E_LIMIT;
+        goto fail;
+      }
+      ACHK(dalloc(&p->d_tab32, (size_t)tab_total32));
       for (int i = 0; i < W * W; ++i) {
         const PairDev& P = p->hp[i];
         const size_t n = P.dbox >= 0 ? (size_t)(2 * P.dbox + 1) * (size_t)P.width : 0;
         if (!n) continue;
         HCHK(hipMemcpyAsync(p->d_tab64 + P.tab_off, ptab64[i], n * sizeof(double2), hipMemcpyDeviceToDevice, st));
-        HCHK(hipMemcpyAsync(p->d_tab32 + P.tab_off, ptab32[i], n * sizeof(float2), hipMemcpyDeviceToDevice, st));
+        // FP32 copy in phase-major rows (padding entries are zero)
+        std::vector<float2> nat(n), perm((size_t)(2 * P.dbox + 1) * P.width32, make_float2(0.0f, 0.0f));
+        HCHK(hipMemcpyAsync(nat.data(), ptab32[i], n * sizeof(float2), hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+        for (int r = 0; r < 2 * P.dbox + 1; ++r)
+          for (int u = 0; u < P.width; ++u)
+            perm[(size_t)r * P.width32 + (size_t)(u % P.rw) * P.cw + (size_t)(u / P.rw)] = nat[(size_t)r * P.width + u];
+        HCHK(hipMemcpyAsync(p->d_tab32 + P.tab_off32, perm.data(), perm.size() * sizeof(float2),
+                            hipMemcpyHostToDevice, st));
+        HCHK(hipStreamSynchronize(st));
       }
       // gamma(k) = <d, conj d> = h_{v,v}(-2k mod M_v, 0) of the truncated auto kernel (Sec. 5.2)
       std::vector<double2> g64;

@@ -31,6 +31,11 @@ struct PairDev {
   int32_t dbox, mu_lo, mu_hi, width;
   int32_t sw, sv;              // a_w / a_min, a_v / a_min
   int64_t tab_off;             // entry offset of the box table
+  // FP32 copy of the table, phase-major rows: entry mu' = mu - mu_lo of row
+  // Delta sits at (mu' mod rw) cw + mu' div rw, so the bins of a target
+  // frame (mu' stepping by rw) read consecutive entries
+  int32_t cw, width32;         // ceil(width / rw), row stride rw cw
+  int64_t tab_off32;           // entry offset in the FP32 table
 };
 
 // One signal of the batch.  Plane of system w: coef_base + off[w], N_w x MR_w

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "mpg_internal.h"
 
 namespace mpg {
@@ -1484,8 +1486,9 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     c.M = Dw.M;
     c.sw_sh = 31 - __clz(P.sw);
     c.rw_sh = 31 - __clz(P.rw);
-    c.pad = 0;
-    c.tab = P.tab_off;
+    c.pad = P.cw;          // FP32 table: phase-major rows
+    c.width = P.width32;
+    c.tab = P.tab_off32;
     c.pad2[0] = c.pad2[1] = 0;
     pc[t] = c;
   }
@@ -1580,12 +1583,12 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     T.k2 = P.mulo - kr;
     T.mspan = P.muhi - P.mulo;
     T.pad[0] = d_gam;  // gamma(m) of target u's bins (lane u holds system u's offset)
-    T.pad[1] = T.pad[2] = 0;
     const int jsv = j * P.sv;
     const int nlo = -((P.dbox - jsv) >> P.sw_sh), nhi = (jsv + P.dbox) >> P.sw_sh;
     const int half = P.M >> 1;
     // bins m in [0, M/2] with m r_w in +-k r_v + [mu_lo, mu_hi] (mod M_max)
     int mlo = 1 << 30, mhi = -1;
+    bool t2 = false;  // term 2 (the conjugate partner) reaches a bin of target u
 #pragma unroll
     for (int term = 0; term < 2; ++term) {
       const int base = term == 0 ? kr : -kr;
@@ -1598,9 +1601,11 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
         const bool ok = use && lo <= hi;
         mlo = ok ? min(mlo, lo) : mlo;
         mhi = ok ? max(mhi, hi) : mhi;
+        if (term == 1) t2 = t2 || ok;
       }
     }
     const bool valid = lane < W && P.dbox >= 0 && mhi >= 0 && nhi >= nlo;
+    const bool any2 = __ballot(valid && t2) != 0ull;
     const int nl = nlo < 0 ? nlo + P.N : (nlo >= P.N ? nlo - P.N : nlo);
     T.nlo = nl;
     T.nF = valid ? nhi - nlo + 1 : 0;
@@ -1608,11 +1613,16 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     T.ilo = valid ? mlo >> LOG_ROW : 0;
     T.bpf = valid ? (mhi >> LOG_ROW) - T.ilo + 1 : 1;
     T.rbpf = 1.0f / (float)T.bpf;
-    T.hrow0 = (int)P.tab + (dlo + P.dbox) * P.width;
+    T.pad[1] = __float_as_int(0.5f * T.rbpf);
+    // table rows are phase-major: term t's entries for bins m sit at
+    // phase ((-k_t) mod r_w) of the row, at mu' div r_w
+    const int ph1 = (-T.k1) & (P.rw - 1), ph2 = (-T.k2) & (P.rw - 1);
+    T.hrow0 = (int)P.tab + (dlo + P.dbox) * P.width + ph1 * P.pad;
+    T.pad[2] = (ph2 - ph1) * P.pad;
     T.hstep = P.width * P.sw;
     const uint32_t cph = (uint32_t)(kk * P.amin) & (uint32_t)vmask;
     T.ph0 = (uint32_t)dlo * cph;
-    T.phs = cph * (uint32_t)P.sw;
+    T.phs = (cph * (uint32_t)P.sw) & (uint32_t)vmask;  // phases are taken mod M_v
     const int t_items = valid ? ((T.nF * T.bpf) + 7) & ~7 : 0;  // whole 8-row slots per target
     const int ihi = mhi >> LOG_ROW;
     const int nend = T.nlo + T.nF - 1;
@@ -1685,7 +1695,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       int4* I = reinterpret_cast<int4*>(&itb->p);
       I[0] = make_int4(p, v, kk, j);
       I[1] = make_int4(pair, T_items, TG, 0);
-      I[2] = make_int4(root_v, vmask, partner, 0);
+      I[2] = make_int4(root_v, vmask, partner, (partner && any2) ? 1 : 0);
       itb->cc = cc;
       itb->Et = Et;
     }
@@ -1717,8 +1727,9 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   // A slot is 8 rows; 8 lanes per row, each with 2 adjacent bins m0 = 16 i +
   // 2 rl8 and m0 + 1.  fl bit 0: row in grid, 1/2: bin 0/1 valid, 3/4: term 1
   // of bin 0/1 in the box, 5/6: term 2 of bin 0/1, 7: pedantic score.
-  auto do_batch = [&](const RowT* tg, int qb, int nact, int ibase, int p, bool pair, bool partner,
-                      uint32_t root_off, uint32_t vmask, Cx<float> cc) {
+  auto do_batch = [&](auto has2, uint64_t* o0, uint64_t* o1, const RowT* tg, int qb, int nact, int ibase,
+                      int p, bool pair, uint32_t root_off, uint32_t vmask, Cx<float> cc) {
+    constexpr bool H2 = decltype(has2)::value;  // some bin of this selection sees term 2
     C4f r[SLOTS], gg[SLOTS];
     Cx<float> h1a[SLOTS], h1b[SLOTS], h2a[SLOTS], h2b[SLOTS], ph[SLOTS];
     uint32_t ee[SLOTS], lfi[SLOTS], fl[SLOTS];
@@ -1735,20 +1746,22 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
           T = tg[w];
           cw = w;
         }
-        // row t of target w's grid: frame f, 16-bin block i
+        // row t of target w's grid: frame f = floor(t / bpf), 16-bin block i.
+        // (t + 1/2) / bpf lies at least 1/(2 bpf) from an integer and its
+        // FP32 value is within 2^-23 (t / bpf + 1) of it, so truncation is
+        // exact while t + bpf < 2^22.  All products below are of non-negative
+        // operands under 2^24 (24-bit multiplies).
         const int t = base8 - T.item_base + rid8;
-        int f = (int)((float)t * T.rbpf);
-        f -= f * T.bpf > t ? 1 : 0;
-        f += (f + 1) * T.bpf <= t ? 1 : 0;
-        const int i = T.ilo + t - f * T.bpf;
+        const int f = (int)fmaf((float)t, T.rbpf, __int_as_float(T.pad[1]));
+        const int i = T.ilo + t - (int)__umul24((uint32_t)f, (uint32_t)T.bpf);
         const bool ok = f < T.nF;
         int n = T.nlo + f;
         n -= n >= T.N ? T.N : 0;
-        const int li = T.lbase + n * T.lpf + i;
+        const int li = T.lbase + (int)__umul24((uint32_t)n, (uint32_t)T.lpf) + i;
         const int m0 = (i << LOG_ROW) + 2 * rl8;
         const bool v0 = ok && m0 < T.MR, v1 = ok && m0 + 1 < T.MR;
-        const uint32_t e = (uint32_t)(T.off + n * T.MR + m0);
-        const uint32_t hrow = (uint32_t)(T.hrow0 + f * T.hstep);
+        const uint32_t e = (uint32_t)T.off + __umul24((uint32_t)n, (uint32_t)T.MR) + (uint32_t)m0;
+        const uint32_t hrow = (uint32_t)T.hrow0 + __umul24((uint32_t)f, (uint32_t)T.hstep);
         const uint32_t mm = (uint32_t)T.mm, step = 1u << T.rsh;
         const uint32_t u1 = (uint32_t)((m0 << T.rsh) - T.k1) & mm, u1b = (u1 + step) & mm;
         const uint32_t u2 = (uint32_t)((m0 << T.rsh) - T.k2) & mm, u2b = (u2 + step) & mm;
@@ -1758,11 +1771,14 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
         // every lane loads (out-of-grid lanes from valid stand-in addresses;
         // the second bin of a pair may lie one element past its frame)
         r[sl] = ld_c4(rho + (v0 ? e : (uint32_t)p));
-        h1a[sl] = tabs[i1a ? hrow + u1 : 0u];
-        h1b[sl] = tabs[i1b ? hrow + u1b : 0u];
-        h2a[sl] = tabs[i2a ? hrow + u2 : 0u];
-        h2b[sl] = tabs[i2b ? hrow + u2b : 0u];
-        ph[sl] = roots[root_off + ((T.ph0 + (uint32_t)f * T.phs) & vmask)];
+        h1a[sl] = tabs[i1a ? hrow + (u1 >> T.rsh) : 0u];
+        h1b[sl] = tabs[i1b ? hrow + (u1b >> T.rsh) : 0u];
+        if constexpr (H2) {
+          const uint32_t hrow2 = hrow + (uint32_t)T.pad[2];
+          h2a[sl] = tabs[i2a ? hrow2 + (u2 >> T.rsh) : 0u];
+          h2b[sl] = tabs[i2b ? hrow2 + (u2b >> T.rsh) : 0u];
+        }
+        ph[sl] = roots[root_off + ((T.ph0 + __umul24((uint32_t)f, T.phs)) & vmask)];
         ee[sl] = e;
         lfi[sl] = (uint32_t)li;
         gg[sl] = C4f{0.0f, 0.0f, 0.0f, 0.0f};
@@ -1771,11 +1787,19 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
         const bool pe0 = pedantic && m0 != 0 && m0 != T.MR - 1, pe1 = pedantic && m0 + 1 != T.MR - 1;
         fl[sl] = (ok ? 1u : 0u) | (v0 ? 2u : 0u) | (v1 ? 4u : 0u) | (i1a ? 8u : 0u) | (i1b ? 16u : 0u) |
                  (i2a ? 32u : 0u) | (i2b ? 64u : 0u) | (pe0 ? 128u : 0u) | (pe1 ? 256u : 0u);
-        // touched-group slot of the row's group
+        // touched-group slot of the row's group (wrapped frames, run B, lie
+        // below run A)
         const int g = li >> LOG_GL;
-        gsl[sl] = T.slot_base + ((g >= T.gA_lo && g < T.gA_lo + T.gA_n) ? g - T.gA_lo : T.gA_n + g - T.gB_lo);
+        gsl[sl] = T.slot_base + (g >= T.gA_lo ? g - T.gA_lo : T.gA_n + g - T.gB_lo);
       }
     }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the batch's loads (and the old leaves before them)
+    // the row flags live in VGPRs across the two phases (not as scalar
+    // masks); the old leaves count as arrived from here on
+#pragma unroll
+    for (int sl = 0; sl < SLOTS; ++sl) asm volatile("" : "+v"(fl[sl]));
+#pragma unroll
+    for (int x = 0; x < LPL; ++x) asm volatile("" : "+v"(o0[x]), "+v"(o1[x]));
     uint32_t n_upd = 0, n_blk = 0;
 #pragma unroll
     for (int sl = 0; sl < SLOTS; ++sl) {
@@ -1786,15 +1810,21 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       auto upd = [&](Cx<float> a1, Cx<float> b2, float& re, float& im) {
         const float ar = a1.re * cs - a1.im * sn, ai = a1.re * sn + a1.im * cs;
         float ur = cc.re * ar - cc.im * ai, ui = cc.re * ai + cc.im * ar;
-        const float br = b2.re * cs + b2.im * sn, bi = b2.im * cs - b2.re * sn;
-        ur += cc.re * br + cc.im * bi;
-        ui += cc.re * bi - cc.im * br;
+        if constexpr (H2) {
+          const float br = b2.re * cs + b2.im * sn, bi = b2.im * cs - b2.re * sn;
+          ur += cc.re * br + cc.im * bi;
+          ui += cc.re * bi - cc.im * br;
+        }
         re -= ur;
         im -= ui;
       };
       const Cx<float> z{0.0f, 0.0f};
       const Cx<float> a1 = (fs & 8u) ? h1a[sl] : z, a2 = (fs & 16u) ? h1b[sl] : z;
-      const Cx<float> b1 = ((fs & 32u) && partner) ? h2a[sl] : z, b2 = ((fs & 64u) && partner) ? h2b[sl] : z;
+      Cx<float> b1 = z, b2 = z;
+      if constexpr (H2) {
+        b1 = (fs & 32u) ? h2a[sl] : z;
+        b2 = (fs & 64u) ? h2b[sl] : z;
+      }
       const bool nz0 = (a1.re != 0.0f) | (a1.im != 0.0f) | (b1.re != 0.0f) | (b1.im != 0.0f);
       const bool nz1 = (a2.re != 0.0f) | (a2.im != 0.0f) | (b2.re != 0.0f) | (b2.im != 0.0f);
       C4f rv = r[sl];
@@ -1806,8 +1836,14 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
         else
           rho[ee[sl]] = Cx<float>{rv.x, rv.y};
       }
-      const float s0 = sel_score<float>(rv.x, rv.y, Cx<float>{gg[sl].x, gg[sl].y}, (fs & 128u) != 0);
-      const float s1 = sel_score<float>(rv.z, rv.w, Cx<float>{gg[sl].z, gg[sl].w}, (fs & 256u) != 0);
+      float s0, s1;
+      if (pedantic) {  // uniform
+        s0 = sel_score<float>(rv.x, rv.y, Cx<float>{gg[sl].x, gg[sl].y}, (fs & 128u) != 0);
+        s1 = sel_score<float>(rv.z, rv.w, Cx<float>{gg[sl].z, gg[sl].w}, (fs & 256u) != 0);
+      } else {
+        s0 = rv.x * rv.x + rv.y * rv.y;
+        s1 = rv.z * rv.z + rv.w * rv.w;
+      }
       const uint32_t bits0 = (fs & 2u) ? __float_as_uint(s0) : 0u;
       const uint32_t bits1 = (fs & 4u) ? __float_as_uint(s1) : 0u;
       uint32_t rm = bits0 > bits1 ? bits0 : bits1;
@@ -1858,7 +1894,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     const int T_items = uni_i(cr.I1.y), TG = uni_i(cr.I1.z);
     const uint32_t root_off = (uint32_t)uni_i(cr.I2.x);
     const uint32_t vmask = (uint32_t)uni_i(cr.I2.y);
-    const bool partner = uni_i(cr.I2.z) != 0;
+    const bool has2 = uni_i(cr.I2.w) != 0;
     const int ibase = cr.ibase, sbase = cr.sbase;
     const Cx<float> cc = cr.cc;
     const double Et = cr.Et;
@@ -1880,7 +1916,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     // old leaves are loaded now and consumed after the update
     const int gs0 = wave, gs1 = wave + NW;
     const int g0 = uni_i(cr.g0), g1 = uni_i(cr.g1);
-    uint64_t old0[LPL], old1[LPL];
+    uint64_t old0[LPL] = {}, old1[LPL] = {};
     if (gs0 < TG) {
 #pragma unroll
       for (int x = 0; x < LPL; ++x) old0[x] = leaves[(uint32_t)(g0 * GL + lane + 64 * x)];
@@ -1909,7 +1945,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
 
     // ---- rows: batches of bs slots (8 rows each) from a shared counter,
     // sized so that waves 1..NW-1 take one batch each; wave 0 joins once its
-    // candidate is built.  The first batch is peeled: waiting for its loads
+    // candidate is built.  Each batch waits for all its loads at once, which
     // also completes the old-leaf loads above, so the merge does not wait on
     // this wave's row stores.
     {
@@ -1917,14 +1953,18 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       const int bs = min(SLOTS, max(1, (nslots + NW - 2) / (NW - 1)));
       int qb = grab() * bs;
       if (qb < nslots) {
-        do_batch(tg, qb, min(bs, nslots - qb), ibase, p, pair, partner, root_off, vmask, cc);
-        for (;;) {
+        do {
+          if (has2)
+            do_batch(std::true_type{}, old0, old1, tg, qb, min(bs, nslots - qb), ibase, p, pair, root_off, vmask, cc);
+          else
+            do_batch(std::false_type{}, old0, old1, tg, qb, min(bs, nslots - qb), ibase, p, pair, root_off, vmask,
+                     cc);
           qb = grab() * bs;
-          if (qb >= nslots) break;
-          do_batch(tg, qb, min(bs, nslots - qb), ibase, p, pair, partner, root_off, vmask, cc);
-        }
+        } while (qb < nslots);
       } else {
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+#pragma unroll
+        for (int x = 0; x < LPL; ++x) asm volatile("" : "+v"(old0[x]), "+v"(old1[x]));
       }
     }
     __syncthreads();
@@ -1941,9 +1981,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       uint64_t best = 0ull;
 #pragma unroll
       for (int x = 0; x < LPL; ++x) {
-        const bool w_ = scv[x] != KEY_SENT;
-        if (w_) scratch[gs * GL + lane + 64 * x] = KEY_SENT;
-        best = umax64(best, w_ ? scv[x] : old[x]);
+        scratch[gs * GL + lane + 64 * x] = KEY_SENT;
+        best = umax64(best, scv[x] != KEY_SENT ? scv[x] : old[x]);
       }
       const uint64_t wm = wave_max_key2<float>(best);
       if (lane == 0) {
@@ -2362,12 +2401,12 @@ hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st
     return launch_mp_t<double, 512, 4>(a, grid, preload, st);
   }
   if (a.G == 128) {
-    if (nt == 256) return launch_mp32_t<256, 4, 128>(a, grid, st);
-    return launch_mp32_t<512, 4, 128>(a, grid, st);
+    if (nt == 256) return launch_mp32_t<256, 2, 128>(a, grid, st);
+    return launch_mp32_t<512, 2, 128>(a, grid, st);
   }
   if (a.G == 256) {
-    if (nt == 256) return launch_mp32_t<256, 4, 256>(a, grid, st);
-    return launch_mp32_t<512, 4, 256>(a, grid, st);
+    if (nt == 256) return launch_mp32_t<256, 2, 256>(a, grid, st);
+    return launch_mp32_t<512, 2, 256>(a, grid, st);
   }
   return hipErrorInvalidValue;
 }
