@@ -1418,7 +1418,7 @@ struct __align__(16) It32 {
   double Et;                         // energy decrease of the selection
   int32_t ibase[MAXW];               // first row item of each target
   int32_t sbase[MAXW];               // first touched-group slot of each target
-  int32_t gown[16];                  // group of touched-group slot gs < 2 NW (merged from registers)
+  int32_t glist[64];                 // group of touched-group slot gs < 64
 };
 
 __host__ __device__ constexpr int mp32_groups_padded(int n_groups) { return (n_groups + 511) & ~511; }
@@ -1460,6 +1460,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   const Cx<float>* tabs = reinterpret_cast<const Cx<float>*>(A.tabs);
   const Cx<float>* gams = reinterpret_cast<const Cx<float>*>(A.gammas);
   const Cx<float>* roots = reinterpret_cast<const Cx<float>*>(A.roots);
+  AtomRec* const atoms = A.atoms + S.atom_base;  // read once: the loop stores to global memory
   const int rid8 = lane >> 3, rl8 = lane & 7;
   const bool pedantic = A.pedantic != 0;
 
@@ -1516,9 +1517,9 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   }
   for (int i = threadIdx.x; i < NPRE * GL; i += NT) scratch[i] = KEY_SENT;
   if (threadIdx.x < 4) ckey[threadIdx.x] = 0ull;  // ckey[0..1], tmax[0..1]
-  static_assert(2 * NW <= 16, "owner slots");
-  static_assert(2 * NW <= 16, "owner slots");
   if (threadIdx.x == 0) *rowq = 0;
+  static_assert(2 * NW <= 16, "owner slots");
+  static_assert(2 * NW <= 16, "owner slots");
   __syncthreads();
 
   SigState st = A.state[s];
@@ -1650,22 +1651,15 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       itb->ibase[lane] = ib;
       itb->sbase[lane] = sb;
     }
-    // group of touched-group slot gs = lane
+    // group of touched-group slot gs = lane: target ws is the last one whose
+    // first slot is at or before gs (its geometry read back from LDS)
     {
-      int alo = 0, an = 0, blo = 0, sbw = 0;
-      for (int w = 0; w < W; ++w) {
-        const int s_b = (int)rdlane32((uint32_t)sb, w);
-        const int a_lo = (int)rdlane32((uint32_t)T.gA_lo, w), a_n = (int)rdlane32((uint32_t)T.gA_n, w);
-        const int b_lo = (int)rdlane32((uint32_t)T.gB_lo, w);
-        const bool mine = s_b <= lane;  // the last target starting at or before slot lane
-        alo = mine ? a_lo : alo;
-        an = mine ? a_n : an;
-        blo = mine ? b_lo : blo;
-        sbw = mine ? s_b : sbw;
-      }
-      const int c = lane - sbw;
-      const int g = c < an ? alo + c : blo + (c - an);
-      if (lane < NPRE) itb->gown[lane] = lane < TG ? g : 0;
+      int ws = 0;
+      for (int w = 1; w < W; ++w) ws += (int)rdlane32((uint32_t)sb, w) <= lane ? 1 : 0;
+      const int4 ga = *reinterpret_cast<const int4*>(&tgb[ws].gA_lo);
+      const int c = lane - tgb[ws].slot_base;
+      const int g = c < ga.y ? ga.x + c : ga.z + (c - ga.y);
+      itb->glist[lane] = lane < TG ? g : 0;
     }
     // coefficient adjustment for the pair, Eq. (dualatprod), and energy
     // decrease, Eq. (projenfaster)
@@ -1718,8 +1712,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     r.Et = itb->Et;
     r.ibase = lane < W ? itb->ibase[lane] : 0x7fffffff;
     r.sbase = lane < W ? itb->sbase[lane] : 0x7fffffff;
-    r.g0 = itb->gown[wave];
-    r.g1 = itb->gown[wave + NW];
+    r.g0 = itb->glist[wave];
+    r.g1 = itb->glist[wave + NW];
     return r;
   };
 
@@ -1898,7 +1892,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     const int ibase = cr.ibase, sbase = cr.sbase;
     const Cx<float> cc = cr.cc;
     const double Et = cr.Et;
-    if (wave == 0 && lane == 0) {
+    if (wave == NW - 1 && lane == 0) {  // wave 0 is busy with the next candidate
       AtomRec ar;
       ar.w = cr.I0.y;
       ar.m = cr.I0.z;
@@ -1907,7 +1901,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       ar.re = (double)cc.re;
       ar.im = (double)cc.im;
       ar.E_after = E - Et;
-      A.atoms[S.atom_base + k] = ar;
+      atoms[k] = ar;
     }
     E -= Et;
     ++k;
@@ -1931,11 +1925,15 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     // the maximum over the others cannot change in this update, so it is the
     // next selection unless a touched group ends above it.
     if (wave == 0) {
-      for (int w = 0; w < W; ++w) {
-        const int4 a = *reinterpret_cast<const int4*>(&tg[w].gA_lo);
-        const int alo = uni_i(a.x), an = uni_i(a.y), blo = uni_i(a.z), bn = uni_i(a.w);
-        for (int i = lane; i < an; i += 64) gkey[alo + i] = 0ull;
-        for (int i = lane; i < bn; i += 64) gkey[blo + i] = 0ull;
+      if (TG <= 64) {
+        if (lane < TG) gkey[it2[cur].glist[lane]] = 0ull;
+      } else {
+        for (int w = 0; w < W; ++w) {
+          const int4 a = *reinterpret_cast<const int4*>(&tg[w].gA_lo);
+          const int alo = uni_i(a.x), an = uni_i(a.y), blo = uni_i(a.z), bn = uni_i(a.w);
+          for (int i = lane; i < an; i += 64) gkey[alo + i] = 0ull;
+          for (int i = lane; i < bn; i += 64) gkey[blo + i] = 0ull;
+        }
       }
       const uint64_t bk = scan_root();
       select_into(bk, cur ^ 1);
@@ -1955,7 +1953,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       if (qb < nslots) {
         do {
           if (has2)
-            do_batch(std::true_type{}, old0, old1, tg, qb, min(bs, nslots - qb), ibase, p, pair, root_off, vmask, cc);
+            do_batch(std::true_type{}, old0, old1, tg, qb, min(bs, nslots - qb), ibase, p, pair, root_off, vmask,
+                     cc);
           else
             do_batch(std::false_type{}, old0, old1, tg, qb, min(bs, nslots - qb), ibase, p, pair, root_off, vmask,
                      cc);
@@ -1995,10 +1994,15 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     if (gs1 < TG) merge_slot(gs1, g1, old1);
     // slots beyond the preloaded ones: the leaves in global memory are current
     for (int gs = NPRE + wave; gs < TG; gs += NW) {
-      const int w = uni_i(__popcll(__ballot(sbase <= gs)) - 1);
-      const int4 a = *reinterpret_cast<const int4*>(&tg[w].gA_lo);
-      const int c = gs - tg[w].slot_base;
-      const int g = uni_i(c < a.y ? a.x + c : a.z + (c - a.y));
+      int g;
+      if (gs < 64) {
+        g = uni_i(it2[cur].glist[gs]);
+      } else {
+        const int w = uni_i(__popcll(__ballot(sbase <= gs)) - 1);
+        const int4 a = *reinterpret_cast<const int4*>(&tg[w].gA_lo);
+        const int c = gs - tg[w].slot_base;
+        g = uni_i(c < a.y ? a.x + c : a.z + (c - a.y));
+      }
       uint64_t best = 0ull;
 #pragma unroll
       for (int x = 0; x < LPL; ++x) best = umax64(best, leaves[(uint32_t)(g * GL + lane + 64 * x)]);
