@@ -12,6 +12,7 @@ from . import build as _build
 
 WIN_BLACKMAN = 0
 WIN_HANN = 1
+WIN_GAUSS = 2      # exp(-pi t^2 / (a M)): its width depends on the lattice
 THR_REL = 1
 CONJ_GATE_GAMMA = 2
 PEDANTIC = 4
@@ -40,6 +41,7 @@ def lib():
         dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
         ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
         _lib.orc_window.argtypes = [C.c_int32, C.c_int32, dp]
+        _lib.orc_window_ga.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp]
         _lib.orc_check_dicts.argtypes = [C.POINTER(_Dict), C.c_int32]
         _lib.orc_padded_length.argtypes = [C.POINTER(_Dict), C.c_int32, C.c_int64]
         _lib.orc_padded_length.restype = C.c_int64
@@ -73,9 +75,10 @@ def _check(rc):
         raise RuntimeError("oracle error %d" % rc)
 
 
-def window(win: int, gl: int) -> np.ndarray:
+def window(win: int, gl: int, a: int = 0, M: int = 0) -> np.ndarray:
+    """Window of a dictionary (win, gl, a, M); a and M matter for the Gaussian."""
     g = np.zeros(gl)
-    _check(lib().orc_window(win, gl, g))
+    _check(lib().orc_window_ga(win, gl, a, M, g))
     return g
 
 

@@ -48,11 +48,15 @@ static int64_t cmod64(int64_t v, int64_t n) {
 
 /* ------------------------------------------------------------------------ */
 /* windows.  The paper fixes only that the window is real with unit 2-norm
- * (Sec. 2.1) and uses Blackman (or Hann) windows of length gl (Sec. 6).  We
- * sample the periodic window centred at t = 0 on t = -gl/2 .. gl/2-1.      */
+ * (Sec. 2.1) and uses Blackman (or Hann) windows of length gl (Sec. 6); its
+ * kernel figure (Sec. 4.1) also shows a Gaussian window without giving its
+ * width.  We sample the window centred at t = 0 on t = -gl/2 .. gl/2-1.
+ * Gaussian (a reading): exp(-pi t^2 / (a M)), the Gaussian whose time and
+ * frequency spreads match the lattice (a, M); truncated to gl samples.     */
 
-int orc_window(int32_t type, int32_t gl, double *g) {
+int orc_window_ga(int32_t type, int32_t gl, int32_t a, int32_t M, double *g) {
   if (gl <= 0 || (gl & 1) || !g) return ORC_E_ARG;
+  if (type == ORC_WIN_GAUSS && ((int64_t)a * M <= 0)) return ORC_E_ARG;
   double nrm = 0.0;
   for (int32_t i = 0; i < gl; ++i) {
     double t = (double)(i - gl / 2);
@@ -61,6 +65,8 @@ int orc_window(int32_t type, int32_t gl, double *g) {
       v = 0.42 + 0.5 * cos(2.0 * M_PI * t / gl) + 0.08 * cos(4.0 * M_PI * t / gl);
     else if (type == ORC_WIN_HANN)
       v = 0.5 + 0.5 * cos(2.0 * M_PI * t / gl);
+    else if (type == ORC_WIN_GAUSS)
+      v = exp(-M_PI * t * t / ((double)a * (double)M));
     else
       return ORC_E_ARG;
     g[i] = v;
@@ -70,6 +76,8 @@ int orc_window(int32_t type, int32_t gl, double *g) {
   for (int32_t i = 0; i < gl; ++i) g[i] /= nrm;
   return ORC_OK;
 }
+
+int orc_window(int32_t type, int32_t gl, double *g) { return orc_window_ga(type, gl, 0, 0, g); }
 
 /* g(t) for any integer t: zero outside [-gl/2, gl/2) */
 static double win_at(const double *g, int32_t gl, int64_t t) {
@@ -81,16 +89,17 @@ static double win_at(const double *g, int32_t gl, int64_t t) {
 /* grid rules (Sec. 2.1): every pair of hops divides the larger one, every
  * pair of channel counts divides the larger one, and M_w / a_w is an integer.
  * Additionally (readings of this implementation): M is a power of two,
- * gl is even and gl <= M.                                                  */
+ * gl is even and gl <= 8 M (a window longer than M is folded modulo M).    */
 
 int orc_check_dicts(const orc_dict *d, int32_t W) {
   if (!d || W <= 0) return ORC_E_ARG;
   for (int32_t w = 0; w < W; ++w) {
-    if (d[w].window != ORC_WIN_BLACKMAN && d[w].window != ORC_WIN_HANN)
+    if (d[w].window != ORC_WIN_BLACKMAN && d[w].window != ORC_WIN_HANN &&
+        d[w].window != ORC_WIN_GAUSS)
       return ORC_E_ARG;
     if (d[w].a <= 0 || d[w].M <= 0 || d[w].gl <= 0) return ORC_E_ARG;
     if (!is_pow2(d[w].M) || d[w].M < 2) return ORC_E_GRID;
-    if ((d[w].gl & 1) || d[w].gl > d[w].M) return ORC_E_GRID;
+    if ((d[w].gl & 1) || d[w].gl > 8 * d[w].M) return ORC_E_GRID;
     if (d[w].M % d[w].a) return ORC_E_GRID;
   }
   for (int32_t w = 0; w < W; ++w)
@@ -177,12 +186,13 @@ int orc_dgt(const orc_dict *d, const double *x, int64_t L, double *re,
     free(g), free(br), free(bi);
     return ORC_E_NOMEM;
   }
-  orc_window(d->window, gl, g);
+  orc_window_ga(d->window, gl, d->a, d->M, g);
   for (int64_t n = 0; n < N; ++n) {
     memset(br, 0, sizeof(double) * M);
     memset(bi, 0, sizeof(double) * M);
+    /* the windowed frame laid out circularly: t mod M (folded when gl > M) */
     for (int32_t t = -gl / 2; t < gl / 2; ++t)
-      br[mod64(t, M)] = x[mod64(n * d->a + t, L)] * g[t + gl / 2];
+      br[mod64(t, M)] += x[mod64(n * d->a + t, L)] * g[t + gl / 2];
     orc_fft(M, br, bi, -1);
     for (int32_t m = 0; m < MR; ++m) {
       re[n * MR + m] = br[m];
@@ -201,7 +211,7 @@ int orc_dgt_direct(const orc_dict *d, const double *x, int64_t L, double *re,
   const int64_t N = L / d->a;
   double *g = malloc(sizeof(double) * gl);
   if (!g) return ORC_E_NOMEM;
-  orc_window(d->window, gl, g);
+  orc_window_ga(d->window, gl, d->a, d->M, g);
   for (int64_t n = 0; n < N; ++n)
     for (int32_t m = 0; m < MR; ++m) {
       double sr = 0.0, si = 0.0;
@@ -236,8 +246,8 @@ int orc_kernel_direct(const orc_dict *dw, const orc_dict *dv, int64_t mu,
     free(gw), free(gv);
     return ORC_E_NOMEM;
   }
-  orc_window(dw->window, dw->gl, gw);
-  orc_window(dv->window, dv->gl, gv);
+  orc_window_ga(dw->window, dw->gl, dw->a, dw->M, gw);
+  orc_window_ga(dv->window, dv->gl, dv->a, dv->M, gv);
   double sr = 0.0, si = 0.0;
   for (int64_t t = -dv->gl / 2; t < dv->gl / 2; ++t) {
     double p = win_at(gv, dv->gl, t) * win_at(gw, dw->gl, t - Delta);
@@ -272,8 +282,8 @@ int orc_kernel_table(const orc_dict *dw, const orc_dict *dv, double eps,
     free(gw), free(gv);
     return ORC_E_NOMEM;
   }
-  orc_window(dw->window, dw->gl, gw);
-  orc_window(dv->window, dv->gl, gv);
+  orc_window_ga(dw->window, dw->gl, dw->a, dw->M, gw);
+  orc_window_ga(dv->window, dv->gl, dv->a, dv->M, gv);
   const int64_t ncol = 2 * (int64_t)D + 1;
   for (int64_t c = 0; c < ncol; ++c) {
     int64_t Delta = (c - D) * amin;
@@ -281,7 +291,7 @@ int orc_kernel_table(const orc_dict *dw, const orc_dict *dv, double eps,
     memset(cr, 0, sizeof(double) * Mmax);
     memset(ci, 0, sizeof(double) * Mmax);
     for (int64_t s = -dw->gl / 2; s < dw->gl / 2; ++s)
-      cr[mod64(s, Mmax)] = win_at(gv, dv->gl, s + Delta) * win_at(gw, dw->gl, s);
+      cr[mod64(s, Mmax)] += win_at(gv, dv->gl, s + Delta) * win_at(gw, dw->gl, s);
     orc_fft(Mmax, cr, ci, -1);
   }
   double thr = eps;
@@ -614,7 +624,7 @@ int orc_resynth(const orc_dict *d, int32_t W, int64_t Lp, int64_t n_atoms,
       free(g);
       return ORC_E_NOMEM;
     }
-    orc_window(d[w].window, d[w].gl, g[w]);
+    orc_window_ga(d[w].window, d[w].gl, d[w].a, d[w].M, g[w]);
   }
   memset(y, 0, sizeof(double) * (size_t)Lp);
   for (int64_t i = 0; i < n_atoms; ++i) {

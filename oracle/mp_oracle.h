@@ -22,6 +22,7 @@ extern "C" {
 /* window shapes */
 #define ORC_WIN_BLACKMAN 0
 #define ORC_WIN_HANN 1
+#define ORC_WIN_GAUSS 2 /* exp(-pi t^2 / (a M)), a reading: see orc_window_ga */
 
 /* flags for orc_mp */
 #define ORC_THR_REL 1u         /* threshold relative to each kernel's peak   */
@@ -56,6 +57,8 @@ typedef struct {
 
 /* Unit-norm window sampled at t = -gl/2 .. gl/2-1; g[i] holds t = i - gl/2. */
 int orc_window(int32_t type, int32_t gl, double *g);
+/* as orc_window; the Gaussian's width depends on the lattice (a, M) */
+int orc_window_ga(int32_t type, int32_t gl, int32_t a, int32_t M, double *g);
 
 /* Grid validation (nested a, nested M, M/a integer) and padded length. */
 int orc_check_dicts(const orc_dict *d, int32_t W);

@@ -11,13 +11,15 @@ coefficient-domain oracle must reproduce this sequence exactly.
 import numpy as np
 
 
-def _window(win: int, gl: int) -> np.ndarray:
-    # independent restatement of the centred periodic windows, unit 2-norm
+def _window(win: int, gl: int, a: int, M: int) -> np.ndarray:
+    # independent restatement of the centred windows, unit 2-norm
     t = np.arange(gl) - gl // 2
     if win == 0:
         g = 0.42 + 0.5 * np.cos(2 * np.pi * t / gl) + 0.08 * np.cos(4 * np.pi * t / gl)
     elif win == 1:
         g = 0.5 + 0.5 * np.cos(2 * np.pi * t / gl)
+    elif win == 2:
+        g = np.exp(-np.pi * t.astype(np.float64) ** 2 / (a * M))
     else:
         raise ValueError(win)
     return g / np.linalg.norm(g)
@@ -26,7 +28,7 @@ def _window(win: int, gl: int) -> np.ndarray:
 def atom(d, m: int, n: int, L: int) -> np.ndarray:
     """d_{m,n}(l) = g(l - n a) exp(2 pi i m (l - n a) / M), circular in l (Eq. gabdict)."""
     win, gl, a, M = d
-    g = _window(win, gl)
+    g = _window(win, gl, a, M)
     out = np.zeros(L, np.complex128)
     t = np.arange(-gl // 2, gl // 2)
     l = (n * a + t) % L

@@ -27,8 +27,9 @@ def _cmod(v, n):
 def test_p1_fig1_kernel_boxes():
     gold = json.load(open(os.path.join(GOLD, "fig1_kernel_boxes.json")))
     a, M, gl = gold["a"], gold["M"], gold["gl"]
-    for name, win in (("blackman", O.WIN_BLACKMAN), ("hann", O.WIN_HANN)):
-        d = (win, gl, a, M)
+    for name, win, glw in (("blackman", O.WIN_BLACKMAN, gl), ("hann", O.WIN_HANN, gl),
+                           ("gauss", O.WIN_GAUSS, gold["gauss_gl"])):
+        d = (win, glw, a, M)
         t = O.kernel_table(d, d, gold["relative_threshold"], O.THR_REL)
         assert [2 * t.box_mu + 1, 2 * t.box_delta + 1] == gold["boxes_mu_by_delta"][name]
         # for an auto kernel the peak is ||g||^2 = 1, so absolute == relative
@@ -50,6 +51,21 @@ def test_p1_window_unit_norm_and_shape():
     assert abs(g[64 // 2 + 16] / g[64 // 2] - (0.42 - 0.08) / 1.0) < 1e-14
 
 
+def test_p1_gaussian_window_shape():
+    # even, unit norm, peak at t = 0, and log g a parabola whose curvature is
+    # fixed by the lattice: second differences of log g all equal -2 pi / (a M)
+    for gl, a, M in ((64, 8, 32), (256, 64, 256), (4096, 512, 2048)):
+        g = O.window(O.WIN_GAUSS, gl, a, M)
+        assert abs(np.sum(g * g) - 1.0) < 1e-14
+        assert np.argmax(g) == gl // 2
+        assert np.allclose(g[1:], g[1:][::-1], rtol=1e-14, atol=0)
+        lg = np.log(g)
+        d2 = lg[2:] - 2 * lg[1:-1] + lg[:-2]
+        assert np.max(np.abs(d2 + 2 * np.pi / (a * M))) < 1e-9
+    with pytest.raises(RuntimeError):
+        O.window(O.WIN_GAUSS, 64)          # the Gaussian needs its lattice
+
+
 # --------------------------------------------------------------------------
 # P2: kernels, modulation and phase convention vs brute-force inner products
 
@@ -59,6 +75,8 @@ PAIR_CASES = [
     ((0, 16, 4, 16), (0, 16, 4, 16)),
     ((1, 32, 16, 32), (0, 16, 4, 16)),
     ((0, 16, 8, 32), (0, 32, 8, 32)),   # gl < M
+    ((2, 64, 8, 32), (0, 16, 4, 16)),   # Gaussian, gl > M (folded)
+    ((2, 32, 4, 16), (2, 64, 8, 32)),   # two Gaussians, both longer than M
 ]
 
 
@@ -118,7 +136,8 @@ def test_p2_kernel_conjugate_symmetry():
 # --------------------------------------------------------------------------
 # P3: DGT
 
-@pytest.mark.parametrize("d", [(0, 16, 4, 16), (0, 32, 8, 64), (1, 64, 16, 64)])
+@pytest.mark.parametrize("d", [(0, 16, 4, 16), (0, 32, 8, 64), (1, 64, 16, 64), (2, 64, 8, 32),
+                               (0, 48, 8, 16)])
 def test_p3_dgt_direct_fft_numpy(d):
     L = 256
     x = np.random.default_rng(2).standard_normal(L)
@@ -127,11 +146,11 @@ def test_p3_dgt_direct_fft_numpy(d):
     assert np.max(np.abs(c1 - c2)) < 1e-12
     # numpy FFT of the circularly laid out windowed frame
     win, gl, a, M = d
-    g = O.window(win, gl)
+    g = O.window(win, gl, a, M)
     t = np.arange(-gl // 2, gl // 2)
     for n in range(L // a):
         buf = np.zeros(M)
-        buf[t % M] = x[(n * a + t) % L] * g
+        np.add.at(buf, t % M, x[(n * a + t) % L] * g)   # folded when gl > M
         ref = np.fft.fft(buf)[: M // 2 + 1]
         assert np.max(np.abs(ref - c1[n])) < 1e-12
     # and the brute-force dictionary
@@ -213,6 +232,7 @@ P5_CASES = [
     ([(1, 32, 8, 64), (0, 64, 16, 64)], 256, 3),
     ([(0, 32, 16, 32), (0, 64, 16, 64)], 256, 4),
     ([(0, 64, 16, 64), (0, 128, 32, 128)], 1024, 5),
+    ([(2, 64, 8, 32), (0, 32, 8, 32)], 256, 6),       # Gaussian longer than M
 ]
 
 
@@ -392,7 +412,9 @@ def test_stop_rules_and_errors():
     # grids
     assert O.check_dicts([(0, 64, 16, 64), (0, 64, 24, 96)]) != 0     # M not power of 2
     assert O.check_dicts([(0, 64, 16, 64), (0, 128, 48, 128)]) != 0   # a not nested
-    assert O.check_dicts([(0, 128, 16, 64)]) != 0                     # gl > M
+    assert O.check_dicts([(0, 128, 16, 64)]) == 0                     # gl > M: folded
+    assert O.check_dicts([(0, 1024, 16, 64)]) != 0                    # gl > 8 M
+    assert O.check_dicts([(3, 64, 16, 64)]) != 0                      # unknown window
     assert O.check_dicts([(0, 64, 48, 64)]) != 0                      # M/a not integer
     assert O.padded_length([(0, 64, 16, 64)], 100) == 128
     assert O.padded_length([(0, 256, 64, 256), (0, 4096, 1024, 4096)], 441000) == 442368
