@@ -40,7 +40,7 @@ extern "C" {
 #define MP_OK 0
 #define MP_E_ARG (-1)   /* invalid argument (null pointer, bad size, bad index) */
 #define MP_E_GRID (-2)  /* systems not compatible: a or M not nested, M/a not integer,
-                           M not a power of two, gl odd or gl > M (Sec. 2.1)      */
+                           M not a power of two, gl odd or gl > 8 M (Sec. 2.1)    */
 #define MP_E_LEN (-3)   /* a padded length is shorter than gl_v + gl_w of some pair  */
 #define MP_E_NOMEM (-4) /* device or host allocation failed                         */
 #define MP_E_HIP (-5)   /* a HIP runtime call failed                                */
@@ -50,6 +50,7 @@ extern "C" {
 /* ---- windows ---- */
 #define MP_WIN_BLACKMAN 0
 #define MP_WIN_HANN 1
+#define MP_WIN_GAUSS 2 /* exp(-pi t^2 / (a M)): spreads matched to the lattice (a, M) */
 
 /* ---- plan flags ---- */
 #define MP_PREC_F32 0x0u         /* FP32 planes, kernels and updates (default)      */
@@ -82,7 +83,8 @@ extern "C" {
 typedef struct mp_plan mp_plan;
 
 /* One Gabor system (g, a, M): window shape, window length gl, hop a and
- * number of channels M (Sec. 2.1, Eq. gabdict). */
+ * number of channels M (Sec. 2.1, Eq. gabdict).  gl is even; a window longer
+ * than M (up to 8 M) is folded modulo M in the analysis. */
 typedef struct {
   int32_t window, gl, a, M;
 } mp_dict;

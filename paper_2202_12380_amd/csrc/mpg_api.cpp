@@ -137,15 +137,21 @@ hipError_t dalloc(T** p, size_t n) {
 }
 
 // Centred periodic window on t = -gl/2 .. gl/2-1, unit 2-norm (Sec. 2.1).
-void make_window(int type, int gl, std::vector<double>& g) {
+// Gaussian (the width is a reading; the paper's kernel figure names the window
+// only): exp(-pi t^2 / (a M)), time and frequency spreads matched to the lattice.
+void make_window(int type, int gl, int a, int M, std::vector<double>& g) {
   g.resize(gl);
   const double pi = 3.14159265358979323846;
   double e = 0.0;
   for (int i = 0; i < gl; ++i) {
     const double t = (double)(i - gl / 2);
-    double v = type == MP_WIN_BLACKMAN
-                   ? 0.42 + 0.5 * std::cos(2.0 * pi * t / gl) + 0.08 * std::cos(4.0 * pi * t / gl)
-                   : 0.5 + 0.5 * std::cos(2.0 * pi * t / gl);
+    double v;
+    if (type == MP_WIN_BLACKMAN)
+      v = 0.42 + 0.5 * std::cos(2.0 * pi * t / gl) + 0.08 * std::cos(4.0 * pi * t / gl);
+    else if (type == MP_WIN_HANN)
+      v = 0.5 + 0.5 * std::cos(2.0 * pi * t / gl);
+    else
+      v = std::exp(-pi * t * t / ((double)a * (double)M));
     g[i] = v;
     e += v * v;
   }
@@ -189,10 +195,11 @@ void free_plan(mp_plan* p) {
 
 int check_dicts(const mp_dict* d, int W) {
   for (int w = 0; w < W; ++w) {
-    if (d[w].window != MP_WIN_BLACKMAN && d[w].window != MP_WIN_HANN) return MP_E_ARG;
+    if (d[w].window != MP_WIN_BLACKMAN && d[w].window != MP_WIN_HANN && d[w].window != MP_WIN_GAUSS)
+      return MP_E_ARG;
     if (d[w].gl <= 0 || d[w].a <= 0 || d[w].M <= 0) return MP_E_ARG;
     if (!is_pow2(d[w].M) || d[w].M < 2) return MP_E_GRID;
-    if ((d[w].gl & 1) || d[w].gl > d[w].M) return MP_E_GRID;
+    if ((d[w].gl & 1) || (int64_t)d[w].gl > 8 * (int64_t)d[w].M) return MP_E_GRID;  // longer than M: folded
     if (d[w].M % d[w].a) return MP_E_GRID;
   }
   for (int w = 0; w < W; ++w)
@@ -462,7 +469,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       int64_t twoff = 0, gamoff = 0, rootoff = 0;
       for (int w = 0; w < W; ++w) {
         std::vector<double> g;
-        make_window(dicts[w].window, dicts[w].gl, g);
+        make_window(dicts[w].window, dicts[w].gl, dicts[w].a, dicts[w].M, g);
         DictDev& D = p->hd[w];
         D.gl = dicts[w].gl;
         D.a = dicts[w].a;

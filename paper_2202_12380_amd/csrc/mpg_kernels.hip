@@ -416,7 +416,8 @@ __global__ void __launch_bounds__(256) k_energy(const XT* __restrict__ x, const 
 // --------------------------------------------------------------------------
 // DGT analysis (Sec. 5): for frame n of system w,
 //   rho(m, n) = sum_{t=-gl/2}^{gl/2-1} x(n a + t) g(t) exp(-2 pi i m t / M),
-// the length-M DFT of the windowed frame u laid out circularly (t mod M).
+// the length-M DFT of the windowed frame u laid out circularly (t mod M,
+// samples that share a slot summed when the window is longer than M).
 // u is real, so one complex FFT of length H = M/2 suffices: with
 // z(q) = u(2q) + i u(2q+1) and Z = FFT_H(z),
 //   rho(m) = (Z(m) + conj Z(H-m)) / 2 + e^{-2 pi i m / M} (Z(m) - conj Z(H-m)) / (2i),
@@ -454,11 +455,13 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
     for (int e = 0; e < 2; ++e) {
       const int i = 2 * q + e;
       const int t = i < H ? i : i - M;
+      // window samples t, t -+ M, ... inside [-gl/2, gl/2) fold onto slot i
       R v = (R)0;
-      if (t >= -gl / 2 && t < gl / 2) {
-        int64_t l = (n * a + t) % Lp;
+      for (int tt = t - ((t + gl / 2) / M) * M; tt < gl / 2; tt += M) {
+        if (tt < -gl / 2) continue;
+        int64_t l = (n * a + tt) % Lp;
         if (l < 0) l += Lp;
-        if (l < L) v = (R)xs[l] * win[t + gl / 2];
+        if (l < L) v += (R)xs[l] * win[tt + gl / 2];
       }
       v2[e] = v;
     }
@@ -653,11 +656,13 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
     for (int e = 0; e < 2; ++e) {
       const int i = 2 * q + e;
       const int t = i < H ? i : i - M;
+      // window samples t, t -+ M, ... inside [-gl/2, gl/2) fold onto slot i
       float v = 0.0f;
-      if (t >= -gl / 2 && t < gl / 2) {
-        int64_t l = (n * a + t) % Lp;
+      for (int tt = t - ((t + gl / 2) / M) * M; tt < gl / 2; tt += M) {
+        if (tt < -gl / 2) continue;
+        int64_t l = (n * a + tt) % Lp;
         if (l < 0) l += Lp;
-        if (l < L) v = (float)xs[l] * win[t + gl / 2];
+        if (l < L) v += (float)xs[l] * win[tt + gl / 2];
       }
       v2[e] = v;
     }

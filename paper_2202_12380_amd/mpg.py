@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libmpg.so")
 
 MP_OK = 0
 MP_E_ARG, MP_E_GRID, MP_E_LEN, MP_E_NOMEM, MP_E_HIP, MP_E_STATE, MP_E_LIMIT = range(-1, -8, -1)
-MP_WIN_BLACKMAN, MP_WIN_HANN = 0, 1
+MP_WIN_BLACKMAN, MP_WIN_HANN, MP_WIN_GAUSS = 0, 1, 2
 MP_PREC_F32, MP_PREC_F64 = 0x0, 0x1
 MP_THR_REL, MP_CONJ_GATE_GAMMA = 0x10, 0x20
 MP_DFT_F16SPLIT, MP_DFT_BF16SPLIT = 0x40, 0x80

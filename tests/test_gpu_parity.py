@@ -25,6 +25,8 @@ def _torch():
     [(0, 512, 128, 512)],
     [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)],
     [(1, 64, 16, 64), (0, 128, 64, 256)],
+    [(2, 4096, 512, 2048)],                        # the Gaussian of the kernel figure
+    [(2, 64, 8, 32), (0, 96, 16, 64)],             # windows longer than M
 ])
 @pytest.mark.parametrize("eps,rel", [(1e-4, False), (1e-3, True)])
 def test_kernel_tables_match_oracle(dicts, eps, rel):
@@ -60,6 +62,7 @@ def test_kernel_tables_match_oracle(dicts, eps, rel):
     ([(0, 512, 128, 512)], 16384),
     ([(0, 64, 16, 64), (0, 256, 64, 256)], 3000),     # ragged: padded to 3072
     ([(1, 32, 8, 32), (0, 128, 32, 128), (0, 128, 128, 512)], 1024),
+    ([(2, 256, 32, 128), (0, 96, 16, 64), (2, 64, 64, 64)], 2048),   # folded windows
 ])
 def test_dgt_planes(prec, dicts, L):
     torch = _torch()
@@ -91,6 +94,7 @@ def test_dgt_planes(prec, dicts, L):
     ([(1, 32, 8, 32), (0, 128, 32, 128), (0, 128, 128, 512)], 1024),
     ([(0, 16384, 4096, 16384), (0, 4096, 1024, 4096)], 1 << 16),
     ([(0, 4, 2, 4), (0, 8, 2, 8)], 64),
+    ([(2, 256, 32, 128), (0, 96, 16, 64)], 2048),                    # folded windows
 ])
 def test_dgt_planes_split_mfma(fmt, tol, dicts, L):
     # DFT on matrix cores with FP16 (0x40) or BF16 (0x80) hi/lo operand pairs;
@@ -130,6 +134,7 @@ def test_mp_fp64_c1_identical():
     ([(1, 32, 8, 32), (0, 128, 32, 128), (0, 128, 128, 512)], 1024, 1e-5, 300),
     ([(0, 64, 16, 64)], 128, 1e-4, 60),                 # shortest allowed length, wraps
     ([(0, 16, 4, 16), (0, 32, 8, 32)], 128, 0.0, 120),  # eps = 0: full kernels
+    ([(2, 128, 16, 64), (0, 96, 16, 64), (2, 512, 64, 256)], 4096, 1e-4, 400),  # Gaussian, gl > M
 ])
 def test_mp_fp64_identical(dicts, L, eps, K):
     _torch()
@@ -189,6 +194,18 @@ def test_mp_split_dft_batch(fmt, gap_tol, e_tol):
     for i, x in enumerate(xs):
         orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32)
         assert_tolerance(ga[i], orc, gap_tol=gap_tol, e_tol=e_tol)
+
+
+def test_mp_fp32_gaussian_long_windows():
+    # Gaussian and Blackman windows longer than M (folded analysis)
+    _torch()
+    dicts = [(2, 512, 64, 256), (0, 2048, 256, 1024), (2, 8192, 512, 4096)]
+    lens = [16384, 17000, 20000]                   # at least 2 gl = 16384
+    xs = [S.audio_like(L, S.rng(78, i)).astype(np.float32) for i, L in enumerate(lens)]
+    _, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=0)
+    for i, x in enumerate(xs):
+        orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32)
+        assert_tolerance(ga[i], orc)
 
 
 def test_mp_fp32_batch_ragged():
