@@ -3,6 +3,7 @@
 TEST INFRASTRUCTURE ONLY: see the package docstring.  Every routine is FP64.
 """
 import ctypes as C
+import math
 from dataclasses import dataclass
 from typing import Sequence
 
@@ -138,7 +139,7 @@ def kernel_table(dw, dv, eps: float, flags: int = 0) -> KernelTable:
     _check(lib().orc_kernel_table(_dicts([dw]), _dicts([dv]), eps, flags, C.byref(D),
                                   re.ctypes.data, im.ctypes.data, C.byref(bm),
                                   C.byref(bd)))
-    return KernelTable(D.value, Mmax, min(dw[2], dv[2]),
+    return KernelTable(D.value, Mmax, math.gcd(dw[2], dv[2]),
                        (re + 1j * im).reshape(2 * D.value + 1, Mmax), bm.value, bd.value)
 
 

@@ -86,10 +86,12 @@ static double win_at(const double *g, int32_t gl, int64_t t) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* grid rules (Sec. 2.1): every pair of hops divides the larger one, every
- * pair of channel counts divides the larger one, and M_w / a_w is an integer.
- * Additionally (readings of this implementation): M is a power of two,
- * gl is even and gl <= 8 M (a window longer than M is folded modulo M).    */
+/* grid rules.  Sec. 2.1 asks only for L to be a multiple of every a (and of
+ * every M); Sec. 4.2 puts a pair of systems on the common grid with time
+ * step gcd(a_w, a_v) and lcm(M_w, M_v) bins.  Readings of this
+ * implementation: M is a power of two (so lcm(M_w, M_v) = max), gl is even
+ * and gl <= 8 M (a window longer than M is folded modulo M).  Hops need not
+ * divide M nor each other.                                                 */
 
 int orc_check_dicts(const orc_dict *d, int32_t W) {
   if (!d || W <= 0) return ORC_E_ARG;
@@ -100,16 +102,7 @@ int orc_check_dicts(const orc_dict *d, int32_t W) {
     if (d[w].a <= 0 || d[w].M <= 0 || d[w].gl <= 0) return ORC_E_ARG;
     if (!is_pow2(d[w].M) || d[w].M < 2) return ORC_E_GRID;
     if ((d[w].gl & 1) || d[w].gl > 8 * d[w].M) return ORC_E_GRID;
-    if (d[w].M % d[w].a) return ORC_E_GRID;
   }
-  for (int32_t w = 0; w < W; ++w)
-    for (int32_t v = 0; v < W; ++v) {
-      int32_t amin = d[w].a < d[v].a ? d[w].a : d[v].a;
-      int32_t amax = d[w].a < d[v].a ? d[v].a : d[w].a;
-      int32_t mmin = d[w].M < d[v].M ? d[w].M : d[v].M;
-      int32_t mmax = d[w].M < d[v].M ? d[v].M : d[w].M;
-      if (amax % amin || mmax % mmin) return ORC_E_GRID;
-    }
   return ORC_OK;
 }
 
@@ -269,7 +262,8 @@ int orc_kernel_direct(const orc_dict *dw, const orc_dict *dv, int64_t mu,
 int orc_kernel_table(const orc_dict *dw, const orc_dict *dv, double eps,
                      uint32_t flags, int32_t *D_out, double *re, double *im,
                      int32_t *box_mu, int32_t *box_delta) {
-  const int32_t amin = dw->a < dv->a ? dw->a : dv->a;
+  /* common grid (Sec. 4.2): time step gcd(a_w, a_v), lcm(M_w, M_v) = max bins */
+  const int32_t amin = (int32_t)gcd64(dw->a, dv->a);
   const int32_t Mmax = dw->M > dv->M ? dw->M : dv->M;
   const int32_t halfsum = (dw->gl + dv->gl) / 2;
   /* largest delta with |delta * amin| < halfsum */
@@ -414,7 +408,7 @@ int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
   for (int32_t w = 0; w < W; ++w)
     for (int32_t v = 0; v < W; ++v) {
       pair_table *t = &T[w * W + v];
-      t->amin = d[w].a < d[v].a ? d[w].a : d[v].a;
+      t->amin = (int32_t)gcd64(d[w].a, d[v].a);
       t->Mmax = d[w].M > d[v].M ? d[w].M : d[v].M;
       orc_kernel_table(&d[w], &d[v], eps, flags, &t->D, NULL, NULL, NULL, NULL);
       size_t n = (size_t)(2 * t->D + 1) * (size_t)t->Mmax;

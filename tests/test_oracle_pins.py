@@ -77,13 +77,17 @@ PAIR_CASES = [
     ((0, 16, 8, 32), (0, 32, 8, 32)),   # gl < M
     ((2, 64, 8, 32), (0, 16, 4, 16)),   # Gaussian, gl > M (folded)
     ((2, 32, 4, 16), (2, 64, 8, 32)),   # two Gaussians, both longer than M
+    ((0, 32, 12, 32), (0, 64, 16, 64)),  # hops 12 / 16: common grid step gcd = 4
+    ((1, 48, 20, 64), (2, 64, 24, 32)),  # hops 20 / 24, neither divides M
 ]
 
 
 @pytest.mark.parametrize("dw,dv", PAIR_CASES)
 def test_p2_kernel_matches_bruteforce_gram(dw, dv):
-    L = 128
+    L = int(np.lcm.reduce([dw[2], dv[2], dw[3], dv[3]]))
+    L *= -(-128 // L)                    # a multiple of every a and M, at least 128
     tab = O.kernel_table(dw, dv, 0.0)
+    assert tab.amin == np.gcd(dw[2], dv[2])
     rng = np.random.default_rng(1)
     rv, rw = tab.Mmax // dv[3], tab.Mmax // dw[3]
     picks = [(0, 0), (dv[3] // 2, 1)] + [(int(rng.integers(0, dv[3] // 2 + 1)),
@@ -137,9 +141,10 @@ def test_p2_kernel_conjugate_symmetry():
 # P3: DGT
 
 @pytest.mark.parametrize("d", [(0, 16, 4, 16), (0, 32, 8, 64), (1, 64, 16, 64), (2, 64, 8, 32),
-                               (0, 48, 8, 16)])
+                               (0, 48, 8, 16), (0, 32, 12, 32), (2, 64, 20, 64)])
 def test_p3_dgt_direct_fft_numpy(d):
-    L = 256
+    L = int(np.lcm(d[2], d[3]))
+    L *= -(-256 // L)
     x = np.random.default_rng(2).standard_normal(L)
     c1 = O.dgt(d, x)
     c2 = O.dgt(d, x, direct=True)
@@ -233,6 +238,8 @@ P5_CASES = [
     ([(0, 32, 16, 32), (0, 64, 16, 64)], 256, 4),
     ([(0, 64, 16, 64), (0, 128, 32, 128)], 1024, 5),
     ([(2, 64, 8, 32), (0, 32, 8, 32)], 256, 6),       # Gaussian longer than M
+    ([(0, 32, 12, 32), (0, 64, 16, 64)], 192, 7),     # hops not nested: gcd grid
+    ([(1, 48, 20, 64), (2, 64, 24, 32)], 960, 8),     # hops dividing neither M
 ]
 
 
@@ -411,11 +418,12 @@ def test_stop_rules_and_errors():
     assert r.n_atoms == 512 // 5
     # grids
     assert O.check_dicts([(0, 64, 16, 64), (0, 64, 24, 96)]) != 0     # M not power of 2
-    assert O.check_dicts([(0, 64, 16, 64), (0, 128, 48, 128)]) != 0   # a not nested
+    assert O.check_dicts([(0, 64, 16, 64), (0, 128, 48, 128)]) == 0   # a not nested: gcd grid
     assert O.check_dicts([(0, 128, 16, 64)]) == 0                     # gl > M: folded
     assert O.check_dicts([(0, 1024, 16, 64)]) != 0                    # gl > 8 M
     assert O.check_dicts([(3, 64, 16, 64)]) != 0                      # unknown window
-    assert O.check_dicts([(0, 64, 48, 64)]) != 0                      # M/a not integer
+    assert O.check_dicts([(0, 64, 48, 64)]) == 0                      # M/a not integer
+    assert O.padded_length([(0, 64, 48, 64)], 100) == 192             # lcm(a, M)
     assert O.padded_length([(0, 64, 16, 64)], 100) == 128
     assert O.padded_length([(0, 256, 64, 256), (0, 4096, 1024, 4096)], 441000) == 442368
     assert O.padded_length([(0, 64, 16, 64)], 64) < 0                 # shorter than 2 gl
