@@ -200,14 +200,9 @@ int check_dicts(const mp_dict* d, int W) {
     if (d[w].gl <= 0 || d[w].a <= 0 || d[w].M <= 0) return MP_E_ARG;
     if (!is_pow2(d[w].M) || d[w].M < 2) return MP_E_GRID;
     if ((d[w].gl & 1) || (int64_t)d[w].gl > 8 * (int64_t)d[w].M) return MP_E_GRID;  // longer than M: folded
-    if (d[w].M % d[w].a) return MP_E_GRID;
   }
-  for (int w = 0; w < W; ++w)
-    for (int v = 0; v < W; ++v) {
-      const int amin = std::min(d[w].a, d[v].a), amax = std::max(d[w].a, d[v].a);
-      const int mmin = std::min(d[w].M, d[v].M), mmax = std::max(d[w].M, d[v].M);
-      if (amax % amin || mmax % mmin) return MP_E_GRID;
-    }
+  // hops need not nest nor divide M: each pair lives on the common grid
+  // gcd(a_w, a_v) x lcm(M_w, M_v) (Sec. 4.2), lcm = max for powers of two
   return MP_OK;
 }
 
@@ -541,7 +536,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       int Mmax_all = 0;
       for (int w = 0; w < W; ++w)
         for (int v = 0; v < W; ++v) {
-          const int amin = std::min(dicts[w].a, dicts[v].a), Mmax = std::max(dicts[w].M, dicts[v].M);
+          const int amin = (int)gcd64(dicts[w].a, dicts[v].a), Mmax = std::max(dicts[w].M, dicts[v].M);
           const int half = (dicts[w].gl + dicts[v].gl) / 2;
           const int D = (half + amin - 1) / amin - 1;
           full_max = std::max(full_max, (size_t)(2 * D + 1) * (size_t)Mmax);
@@ -557,7 +552,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       for (int w = 0; w < W; ++w)
         for (int v = 0; v < W; ++v) {
           const int idx = w * W + v;
-          const int amin = std::min(dicts[w].a, dicts[v].a), Mmax = std::max(dicts[w].M, dicts[v].M);
+          const int amin = (int)gcd64(dicts[w].a, dicts[v].a), Mmax = std::max(dicts[w].M, dicts[v].M);
           const int half = (dicts[w].gl + dicts[v].gl) / 2;
           const int D = (half + amin - 1) / amin - 1;
           HCHK(launch_roots(Mmax, Mmax, -1, d_roots, nullptr, st));

@@ -1401,7 +1401,7 @@ __global__ void __launch_bounds__(NT) k_mp(MPArgs A) {
 constexpr uint64_t KEY_SENT = ~0ull;     // scratch entry not written
 
 // Row geometry of one target system for the current selection (LDS).  All M
-// and a are powers of two, so r_w and a_w / a_min are shifts.
+// are powers of two, so r_w = M_max / M_w is a shift.
 struct __align__(16) RowT {
   int32_t MR, N, off, lbase;
   int32_t lpf, nlo, nF, ilo;
@@ -1490,7 +1490,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     c.dbox = P.dbox; c.mulo = P.mu_lo; c.muhi = P.mu_hi; c.width = P.width;
     c.sw = P.sw; c.sv = P.sv; c.Lpa = 0; c.amin = P.amin;
     c.M = Dw.M;
-    c.sw_sh = 31 - __clz(P.sw);
+    c.sw_sh = (P.sw & (P.sw - 1)) ? -1 : (31 - __clz(P.sw));  // -1: a_w / gcd not a power of two
     c.rw_sh = 31 - __clz(P.rw);
     c.pad = P.cw;          // FP32 table: phase-major rows
     c.width = P.width32;
@@ -1590,7 +1590,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     T.mspan = P.muhi - P.mulo;
     T.pad[0] = d_gam;  // gamma(m) of target u's bins (lane u holds system u's offset)
     const int jsv = j * P.sv;
-    const int nlo = -((P.dbox - jsv) >> P.sw_sh), nhi = (jsv + P.dbox) >> P.sw_sh;
+    const int nlo = cdiv_p(jsv - P.dbox, P.sw, P.sw_sh), nhi = fdiv_p(jsv + P.dbox, P.sw, P.sw_sh);
     const int half = P.M >> 1;
     // bins m in [0, M/2] with m r_w in +-k r_v + [mu_lo, mu_hi] (mod M_max)
     int mlo = 1 << 30, mhi = -1;

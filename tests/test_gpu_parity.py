@@ -27,6 +27,7 @@ def _torch():
     [(1, 64, 16, 64), (0, 128, 64, 256)],
     [(2, 4096, 512, 2048)],                        # the Gaussian of the kernel figure
     [(2, 64, 8, 32), (0, 96, 16, 64)],             # windows longer than M
+    [(0, 64, 24, 64), (0, 128, 16, 128)],          # hops not nested: grid step gcd = 8
 ])
 @pytest.mark.parametrize("eps,rel", [(1e-4, False), (1e-3, True)])
 def test_kernel_tables_match_oracle(dicts, eps, rel):
@@ -63,6 +64,7 @@ def test_kernel_tables_match_oracle(dicts, eps, rel):
     ([(0, 64, 16, 64), (0, 256, 64, 256)], 3000),     # ragged: padded to 3072
     ([(1, 32, 8, 32), (0, 128, 32, 128), (0, 128, 128, 512)], 1024),
     ([(2, 256, 32, 128), (0, 96, 16, 64), (2, 64, 64, 64)], 2048),   # folded windows
+    ([(0, 64, 24, 64), (1, 128, 40, 128)], 3000),    # hops dividing neither M: padded to 3840
 ])
 def test_dgt_planes(prec, dicts, L):
     torch = _torch()
@@ -135,6 +137,7 @@ def test_mp_fp64_c1_identical():
     ([(0, 64, 16, 64)], 128, 1e-4, 60),                 # shortest allowed length, wraps
     ([(0, 16, 4, 16), (0, 32, 8, 32)], 128, 0.0, 120),  # eps = 0: full kernels
     ([(2, 128, 16, 64), (0, 96, 16, 64), (2, 512, 64, 256)], 4096, 1e-4, 400),  # Gaussian, gl > M
+    ([(0, 64, 24, 64), (0, 128, 16, 128), (2, 256, 40, 128)], 3840, 1e-4, 400),  # gcd grids
 ])
 def test_mp_fp64_identical(dicts, L, eps, K):
     _torch()
@@ -202,6 +205,18 @@ def test_mp_fp32_gaussian_long_windows():
     dicts = [(2, 512, 64, 256), (0, 2048, 256, 1024), (2, 8192, 512, 4096)]
     lens = [16384, 17000, 20000]                   # at least 2 gl = 16384
     xs = [S.audio_like(L, S.rng(78, i)).astype(np.float32) for i, L in enumerate(lens)]
+    _, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=0)
+    for i, x in enumerate(xs):
+        orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32)
+        assert_tolerance(ga[i], orc)
+
+
+def test_mp_fp32_gcd_grids():
+    # hops 96 and 160 nest neither each other nor their M: common grid step 32
+    _torch()
+    dicts = [(0, 256, 96, 256), (0, 1024, 160, 1024), (2, 512, 64, 256)]
+    lens = [16000, 30000, 15360]
+    xs = [S.audio_like(L, S.rng(79, i)).astype(np.float32) for i, L in enumerate(lens)]
     _, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=0)
     for i, x in enumerate(xs):
         orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32)
