@@ -381,18 +381,27 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
           p->logG += 1;
         }
       } else {
+        // 768 threads (12 waves) unless the group keys and the owners'
+        // scratch only fit the LDS with 512 (or MPG_NT=512 asks for it)
         p->G = 0;
-        int gpref = 256;
+        int gpref = 256, ntpref = 768;
         if (const char* e = getenv("MPG_GL"))
           if (atoi(e) == 128) gpref = 128;
-        for (int G : {128, 256}) {
-          if (G < gpref) continue;
-          const int64_t ng = groups_max(G);
-          if (ng < (1 << 24) && mp_shmem_bytes(false, 512, G, (int)ng) <= 160 * 1024) {
-            p->G = G;
-            p->logG = G == 128 ? 7 : 8;
-            break;
+        if (const char* e = getenv("MPG_NT"))
+          if (atoi(e) == 512) ntpref = 512;
+        for (int nt : {768, 512}) {
+          if (nt > ntpref) continue;
+          for (int G : {128, 256}) {
+            if (G < gpref) continue;
+            const int64_t ng = groups_max(G);
+            if (ng < (1 << 24) && mp_shmem_bytes(false, nt, G, (int)ng) <= 160 * 1024) {
+              p->G = G;
+              p->logG = G == 128 ? 7 : 8;
+              p->nt = nt;
+              break;
+            }
           }
+          if (p->G) break;
         }
         if (!p->G) {
           rc = MP_E_LIMIT;
@@ -731,11 +740,11 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     for (auto& e : p->ev) HCHK(hipEventCreate(&e));
     p->ev_valid = true;
 
-    // launch shape of the MP loop
-    p->nt = 512;
-    if (const char* e = getenv("MPG_NT")) {
-      const int v = atoi(e);
-      if (v == 256 || v == 512) p->nt = v;
+    // launch shape of the MP loop (FP32: chosen with the group size above)
+    if (p->f64) {
+      p->nt = 512;
+      if (const char* e = getenv("MPG_NT"))
+        if (atoi(e) == 256) p->nt = 256;
     }
     p->shmem = mp_shmem_bytes(p->f64, p->nt, p->G, p->n_groups_max);
     if (p->shmem == 0 || p->shmem > 160 * 1024) {

@@ -1523,8 +1523,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   for (int i = threadIdx.x; i < NPRE * GL; i += NT) scratch[i] = KEY_SENT;
   if (threadIdx.x < 4) ckey[threadIdx.x] = 0ull;  // ckey[0..1], tmax[0..1]
   if (threadIdx.x == 0) *rowq = 0;
-  static_assert(2 * NW <= 16, "owner slots");
-  static_assert(2 * NW <= 16, "owner slots");
+  static_assert(2 * NW <= 64, "owner slots are listed in It32::glist");
   __syncthreads();
 
   SigState st = A.state[s];
@@ -2396,8 +2395,9 @@ size_t mp_shmem_bytes(bool f64, int nt, int G, int n_groups_max) {
     return nt == 256 ? mp_lds_bytes<double, 256, 4>(n_groups_max, preload)
                      : mp_lds_bytes<double, 512, 4>(n_groups_max, preload);
   }
-  if (G == 128) return nt == 256 ? mp32_lds_bytes<256, 128>(n_groups_max) : mp32_lds_bytes<512, 128>(n_groups_max);
-  if (G == 256) return nt == 256 ? mp32_lds_bytes<256, 256>(n_groups_max) : mp32_lds_bytes<512, 256>(n_groups_max);
+  if (nt != 512 && nt != 768) return 0;
+  if (G == 128) return nt == 768 ? mp32_lds_bytes<768, 128>(n_groups_max) : mp32_lds_bytes<512, 128>(n_groups_max);
+  if (G == 256) return nt == 768 ? mp32_lds_bytes<768, 256>(n_groups_max) : mp32_lds_bytes<512, 256>(n_groups_max);
   return 0;
 }
 
@@ -2410,11 +2410,11 @@ hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st
     return launch_mp_t<double, 512, 4>(a, grid, preload, st);
   }
   if (a.G == 128) {
-    if (nt == 256) return launch_mp32_t<256, 2, 128>(a, grid, st);
+    if (nt == 768) return launch_mp32_t<768, 2, 128>(a, grid, st);
     return launch_mp32_t<512, 2, 128>(a, grid, st);
   }
   if (a.G == 256) {
-    if (nt == 256) return launch_mp32_t<256, 2, 256>(a, grid, st);
+    if (nt == 768) return launch_mp32_t<768, 2, 256>(a, grid, st);
     return launch_mp32_t<512, 2, 256>(a, grid, st);
   }
   return hipErrorInvalidValue;
