@@ -272,6 +272,9 @@ __device__ __forceinline__ uint64_t wave_max_key2<float>(uint64_t k) {
   h = max_dpp32<0x124>(h);
   h = max_dpp32<0x128>(h);
   uint32_t hm = max(max(rdlane32(h, 0), rdlane32(h, 16)), max(rdlane32(h, 32), rdlane32(h, 48)));
+  // one lane holds the maximum value word (the common case): its index word
+  const uint64_t eq = __ballot(hi == hm);
+  if (__popcll(eq) == 1) return ((uint64_t)hm << 32) | rdlane32((uint32_t)k, (int)__ffsll((unsigned long long)eq) - 1);
   uint32_t lo = hi == hm ? (uint32_t)k : 0u;
   uint32_t l = max_dpp32<0xB1>(lo);
   l = max_dpp32<0x4E>(l);
@@ -1617,7 +1620,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     const int dlo = nlo * P.sw - jsv;  // delta of the first frame, in [-dbox, dbox]
     T.ilo = valid ? mlo >> LOG_ROW : 0;
     T.bpf = valid ? (mhi >> LOG_ROW) - T.ilo + 1 : 1;
-    T.rbpf = 1.0f / (float)T.bpf;
+    T.rbpf = __builtin_amdgcn_rcpf((float)T.bpf);  // within 1 ulp of 1 / bpf
     T.pad[1] = __float_as_int(0.5f * T.rbpf);
     // table rows are phase-major: term t's entries for bins m sit at
     // phase ((-k_t) mod r_w) of the row, at mu' div r_w
@@ -1745,10 +1748,12 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
           cw = w;
         }
         // row t of target w's grid: frame f = floor(t / bpf), 16-bin block i.
-        // (t + 1/2) / bpf lies at least 1/(2 bpf) from an integer and its
-        // FP32 value is within 2^-23 (t / bpf + 1) of it, so truncation is
-        // exact while t + bpf < 2^22.  All products below are of non-negative
-        // operands under 2^24 (24-bit multiplies).
+        // (t + 1/2) / bpf lies at least 1/(2 bpf) from an integer; its FP32
+        // value (reciprocal within 1 ulp, one fma) is within
+        // 1.5 2^-23 (t + 1/2) / bpf of it, so truncation is exact while
+        // t < 2^21 (rows per selection are bounded so at plan creation).
+        // All products below are of non-negative operands under 2^24
+        // (24-bit multiplies).
         const int t = base8 - T.item_base + rid8;
         const int f = (int)fmaf((float)t, T.rbpf, __int_as_float(T.pad[1]));
         const int i = T.ilo + t - (int)__umul24((uint32_t)f, (uint32_t)T.bpf);
@@ -1981,12 +1986,18 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       uint64_t scv[LPL];
 #pragma unroll
       for (int x = 0; x < LPL; ++x) scv[x] = scratch[gs * GL + lane + 64 * x];
-      uint64_t best = 0ull;
+      uint64_t cand[LPL];
 #pragma unroll
       for (int x = 0; x < LPL; ++x) {
         scratch[gs * GL + lane + 64 * x] = KEY_SENT;
-        best = umax64(best, scv[x] != KEY_SENT ? scv[x] : old[x]);
+        cand[x] = scv[x] != KEY_SENT ? scv[x] : old[x];
       }
+      // pairwise tree: depth log2(LPL)
+#pragma unroll
+      for (int w2 = LPL / 2; w2 >= 1; w2 /= 2)
+#pragma unroll
+        for (int x = 0; x < w2; ++x) cand[x] = umax64(cand[x], cand[x + w2]);
+      const uint64_t best = cand[0];
       const uint64_t wm = wave_max_key2<float>(best);
       if (lane == 0) {
         gkey[g] = wm;
