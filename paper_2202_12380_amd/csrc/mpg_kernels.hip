@@ -1501,6 +1501,9 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     c.pad2[0] = c.pad2[1] = 0;
     pc[t] = c;
   }
+  // every pair's a_w / gcd a power of two (nested hops): frame ranges by shifts
+  const bool pow2hops =
+      __ballot(lane < W * W && (A.pairs[lane < W * W ? lane : 0].sw & (A.pairs[lane < W * W ? lane : 0].sw - 1)) != 0) == 0ull;
   // dictionary constants, lane u < W holds system u
   int d_off = 0x7fffffff, d_MR = 1, d_M = 2, d_sh = 0, d_gam = 0, d_root = 0;
   uint32_t d_mul = 0;
@@ -1592,7 +1595,14 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     T.mspan = P.muhi - P.mulo;
     T.pad[0] = d_gam;  // gamma(m) of target u's bins (lane u holds system u's offset)
     const int jsv = j * P.sv;
-    const int nlo = cdiv_p(jsv - P.dbox, P.sw, P.sw_sh), nhi = fdiv_p(jsv + P.dbox, P.sw, P.sw_sh);
+    int nlo, nhi;
+    if (pow2hops) {  // uniform
+      nlo = -((P.dbox - jsv) >> P.sw_sh);
+      nhi = (jsv + P.dbox) >> P.sw_sh;
+    } else {
+      nlo = ceil_div32(jsv - P.dbox, P.sw);
+      nhi = floor_div32(jsv + P.dbox, P.sw);
+    }
     const int half = P.M >> 1;
     // bins m in [0, M/2] with m r_w in +-k r_v + [mu_lo, mu_hi] (mod M_max)
     int mlo = 1 << 30, mhi = -1;
