@@ -1587,14 +1587,14 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     const PairC P = pc[u * W + v];
     RowT T;
     T.MR = P.MR; T.N = P.N; T.off = P.off; T.lbase = P.lbase; T.lpf = P.lpf;
-    const int kr = kk * P.rv;
+    const int kr = (int)__umul24((uint32_t)kk, (uint32_t)P.rv);
     T.rsh = P.rw_sh;
     T.mm = P.Mmax - 1;
     T.k1 = kr + P.mulo;
     T.k2 = P.mulo - kr;
     T.mspan = P.muhi - P.mulo;
     T.pad[0] = d_gam;  // gamma(m) of target u's bins (lane u holds system u's offset)
-    const int jsv = j * P.sv;
+    const int jsv = (int)__umul24((uint32_t)j, (uint32_t)P.sv);
     int nlo, nhi;
     if (pow2hops) {  // uniform
       nlo = -((P.dbox - jsv) >> P.sw_sh);
@@ -1604,7 +1604,9 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       nhi = floor_div32(jsv + P.dbox, P.sw);
     }
     const int half = P.M >> 1;
-    // bins m in [0, M/2] with m r_w in +-k r_v + [mu_lo, mu_hi] (mod M_max)
+    // bins m in [0, M/2] with m r_w in +-k r_v + [mu_lo, mu_hi] (mod M_max):
+    // the bins [A1, B1] of one term, taken mod M (M a power of two), meet
+    // [0, M/2] in at most two pieces, [A1 mod M, .] and the wrapped [0, .]
     int mlo = 1 << 30, mhi = -1;
     bool t2 = false;  // term 2 (the conjugate partner) reaches a bin of target u
 #pragma unroll
@@ -1613,14 +1615,16 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       const int A1 = -((-(base + P.mulo)) >> P.rw_sh), B1 = (base + P.muhi) >> P.rw_sh;
       const bool use = term == 0 || pair;
       const bool full = B1 - A1 + 1 >= P.M;
-#pragma unroll
-      for (int c = -1; c <= 1; ++c) {
-        const int lo = full ? 0 : max(A1 + c * P.M, 0), hi = full ? half : min(B1 + c * P.M, half);
-        const bool ok = use && lo <= hi;
-        mlo = ok ? min(mlo, lo) : mlo;
-        mhi = ok ? max(mhi, hi) : mhi;
-        if (term == 1) t2 = t2 || ok;
-      }
+      const int A1m = A1 & (P.M - 1), B1m = B1 + (A1m - A1);
+      const int lo0 = full ? 0 : A1m, hi0 = full ? half : min(B1m, half);
+      const bool ok0 = use && lo0 <= hi0;
+      const bool ok1 = use && !full && B1m >= P.M;  // piece [0, B1m - M]
+      const int hi1 = min(B1m - P.M, half);
+      mlo = ok0 ? min(mlo, lo0) : mlo;
+      mhi = ok0 ? max(mhi, hi0) : mhi;
+      mlo = ok1 ? 0 : mlo;
+      mhi = ok1 ? max(mhi, hi1) : mhi;
+      if (term == 1) t2 = ok0 || ok1;
     }
     const bool valid = lane < W && P.dbox >= 0 && mhi >= 0 && nhi >= nlo;
     const bool any2 = __ballot(valid && t2) != 0ull;
@@ -1635,13 +1639,14 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     // table rows are phase-major: term t's entries for bins m sit at
     // phase ((-k_t) mod r_w) of the row, at mu' div r_w
     const int ph1 = (-T.k1) & (P.rw - 1), ph2 = (-T.k2) & (P.rw - 1);
-    T.hrow0 = (int)P.tab + (dlo + P.dbox) * P.width + ph1 * P.pad;
-    T.pad[2] = (ph2 - ph1) * P.pad;
-    T.hstep = P.width * P.sw;
-    const uint32_t cph = (uint32_t)(kk * P.amin) & (uint32_t)vmask;
-    T.ph0 = (uint32_t)dlo * cph;
-    T.phs = (cph * (uint32_t)P.sw) & (uint32_t)vmask;  // phases are taken mod M_v
-    const int t_items = valid ? ((T.nF * T.bpf) + 7) & ~7 : 0;  // whole 8-row slots per target
+    T.hrow0 = (int)P.tab + (int)__umul24((uint32_t)(dlo + P.dbox), (uint32_t)P.width) +
+              (int)__umul24((uint32_t)ph1, (uint32_t)P.pad);
+    T.pad[2] = __mul24(ph2 - ph1, P.pad);
+    T.hstep = (int)__umul24((uint32_t)P.width, (uint32_t)P.sw);
+    const uint32_t cph = __umul24((uint32_t)kk, (uint32_t)P.amin) & (uint32_t)vmask;
+    T.ph0 = (uint32_t)__mul24(dlo, (int)cph);                           // taken mod M_v
+    T.phs = __umul24(cph, (uint32_t)P.sw) & (uint32_t)vmask;          // phases are taken mod M_v
+    const int t_items = valid ? ((int)__umul24((uint32_t)T.nF, (uint32_t)T.bpf) + 7) & ~7 : 0;  // whole 8-row slots per target
     const int ihi = mhi >> LOG_ROW;
     const int nend = T.nlo + T.nF - 1;
     const int nAe = min(nend, T.N - 1);
