@@ -223,6 +223,26 @@ def test_mp_fp32_gcd_grids():
         assert_tolerance(ga[i], orc)
 
 
+@pytest.mark.parametrize("env,threads,groups", [
+    ({"MPG_NT": "512"}, 512, 256),                  # the LDS fallback launch shape
+    ({"MPG_GL": "128"}, 768, 128),                  # 128-leaf groups
+])
+def test_mp_fp32_launch_shapes(env, threads, groups, monkeypatch):
+    # the plan's other FP32 launch shapes give the same atoms within the FP32 rule
+    _torch()
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)]
+    lens = [16384, 12345]
+    xs = [S.audio_like(L, S.rng(80, i)).astype(np.float32) for i, L in enumerate(lens)]
+    plan, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=0)
+    st = plan.stats()
+    assert (st.threads, st.group_leaves) == (threads, groups)
+    for i, x in enumerate(xs):
+        orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32)
+        assert_tolerance(ga[i], orc)
+
+
 def test_mp_fp32_batch_ragged():
     _torch()
     dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)]
