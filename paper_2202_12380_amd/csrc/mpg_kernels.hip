@@ -1966,8 +1966,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     }
 
     // ---- rows: batches of bs slots (8 rows each) from a shared counter,
-    // sized so that waves 1..NW-1 take one batch each; wave 0 joins once its
-    // candidate is built.  Each batch waits for all its loads at once, which
+    // sized so that waves 1..NW-1 take one batch each; wave 0 takes what is
+    // left once its candidate is built.  Each batch waits for all its loads at once, which
     // also completes the old-leaf loads above, so the merge does not wait on
     // this wave's row stores.
     {
