@@ -6,11 +6,17 @@
  * Prusa, Holighaus, Balazs, "Fast Matching Pursuit with Multi-Gabor
  * Dictionaries", ACM TOMS 47(3), 2021:
  *   - DGT analysis rho_0 = D* x in every Gabor system (Sec. 5);
- *   - per iteration: the global maximum of |rho|^2 taken from a max tree
+ *   - per iteration: the global maximum of |rho|^2 (or, with MP_PEDANTIC,
+ *     of the real-atom pair projection energy, Sec. 5) taken from a max tree
  *     (Sec. 5.1), the real-atom pair adjustment (Sec. 5, Eqs. dualatprod and
  *     projenfaster), and the residual update by truncated, modulated
  *     cross-kernels (Sec. 4, Eqs. GramKern, hkj, fastkernupdate; Alg. 3);
+ *   - the reset procedure (Alg. 2): approximate MP in rounds, each started
+ *     from the analysis of the true residual (mp_run_resets);
  *   - synthesis of the selected atoms (Sec. 5, Eq. idgtreal).
+ * Systems may use Blackman, Hann or Gaussian windows (windows longer than M
+ * are folded), and hops that neither nest nor divide M: each pair of systems
+ * lives on the common grid gcd(a_w, a_v) x lcm(M_w, M_v) (Sec. 4.2).
  *
  * Conventions.
  *   - Every function returns 0 (MP_OK) or a negative MP_E_* code and never
