@@ -16,13 +16,14 @@
 namespace mpg {
 
 hipError_t launch_roots(int M, int n, int sign, double2* o64, float2* o32, hipStream_t st);
+hipError_t launch_stage_tw(int M, double2* t64, float2* t32, hipStream_t st);
 hipError_t launch_gram_full(const double* gw, int glw, const double* gv, int glv, int amin, int D,
                             int Mmax, const double2* roots, double2* out, hipStream_t st);
 hipError_t launch_gram_absmax(const double2* t, int64_t n, unsigned long long* out, hipStream_t st);
 hipError_t launch_gram_box(const double2* t, int D, int Mmax, double thr, int* box, hipStream_t st);
 hipError_t launch_gram_extract(const double2* t, int D, int Mmax, double thr, int dbox, int mu_lo,
                                int width, double2* o64, float2* o32, hipStream_t st);
-hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch, SigState* st_,
+hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch, double* part, SigState* st_,
                          hipStream_t st);
 hipError_t launch_reset_init(const void* x, int dtype, const SigDev* sigs, int batch, int64_t max_Lp,
                              const int64_t* roff, double* r, hipStream_t st);
@@ -86,6 +87,7 @@ struct mp_plan {
   PairDev* d_pairs = nullptr;
   SigDev* d_sigs = nullptr;
   SigState* d_state = nullptr;
+  double* d_epart = nullptr;  // ENERGY_PARTS partial sums of ||x||^2 per signal
   double* d_win64 = nullptr;
   float* d_win32 = nullptr;
   double2* d_tw64 = nullptr;
@@ -165,6 +167,7 @@ void free_plan(mp_plan* p) {
   hipFree(p->d_pairs);
   hipFree(p->d_sigs);
   hipFree(p->d_state);
+  hipFree(p->d_epart);
   hipFree(p->d_win64);
   hipFree(p->d_win32);
   hipFree(p->d_tw64);
@@ -486,7 +489,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
         magic_u32((uint32_t)D.MR, &D.mr_mul, &D.mr_sh);
         D.lpf = (D.MR + ROW - 1) / ROW;
         D.pad = 0;
-        twoff += std::max(D.M / 2, 1);
+        twoff += std::max(D.M, 2);  // M/2 twiddles, then their stage-major copy
         gamoff += D.MR;
         rootoff += D.M;
         for (double v : g) {
@@ -500,9 +503,11 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       HCHK(hipMemcpy(p->d_win32, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice));
       ACHK(dalloc(&p->d_tw64, (size_t)twoff));
       ACHK(dalloc(&p->d_tw32, (size_t)twoff));
-      for (int w = 0; w < W; ++w)
+      for (int w = 0; w < W; ++w) {
         HCHK(launch_roots(p->hd[w].M, p->hd[w].M / 2, -1, p->d_tw64 + p->hd[w].tw_off,
                           p->d_tw32 + p->hd[w].tw_off, st));
+        HCHK(launch_stage_tw(p->hd[w].M, p->d_tw64 + p->hd[w].tw_off, p->d_tw32 + p->hd[w].tw_off, st));
+      }
       // one entry past the end: the FP32 loop reads gamma of two adjacent bins
       ACHK(dalloc(&p->d_gam64, (size_t)gamoff + 1));
       ACHK(dalloc(&p->d_gam32, (size_t)gamoff + 1));
@@ -707,6 +712,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     HCHK(hipMemcpy(p->d_sigs, p->hs.data(), sizeof(SigDev) * batch, hipMemcpyHostToDevice));
     ACHK(dalloc(&p->d_state, (size_t)batch));
     HCHK(hipMemset(p->d_state, 0, sizeof(SigState) * batch));
+    ACHK(dalloc(&p->d_epart, (size_t)batch * ENERGY_PARTS));
     const size_t cb = p->f64 ? 16 : 8;
     // one coefficient past the end: the FP32 loop reads two adjacent bins
     HCHK(hipMalloc(&p->d_planes, (size_t)(p->total_coef + 1) * cb));
@@ -784,7 +790,7 @@ int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream)
   int rc = MP_OK;
   const void* win = p->f64 ? (const void*)p->d_win64 : (const void*)p->d_win32;
   HCHK(hipEventRecord(p->ev[0], stream));
-  HCHK(launch_energy(x_dev, dtype, p->d_sigs, p->batch, p->d_state, stream));
+  HCHK(launch_energy(x_dev, dtype, p->d_sigs, p->batch, p->d_epart, p->d_state, stream));
   for (int w = 0; w < p->W; ++w) {
     const DictDev& D = p->hd[w];
     const void* tw = p->f64 ? (const void*)(p->d_tw64 + D.tw_off) : (const void*)(p->d_tw32 + D.tw_off);

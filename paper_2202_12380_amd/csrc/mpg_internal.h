@@ -7,6 +7,7 @@ namespace mpg {
 
 constexpr int MAXW = 8;        // Gabor systems per plan
 constexpr int ROW = 16;        // coefficients per max-tree leaf (one DPP row)
+constexpr int ENERGY_PARTS = 32;  // partial sums per signal in the energy kernel
 constexpr int LOG_ROW = 4;
 constexpr int GLEAVES = 256;   // leaves per group when the group preload path is used (FP64)
 
@@ -14,7 +15,8 @@ constexpr int GLEAVES = 256;   // leaves per group when the group preload path i
 struct DictDev {
   int32_t gl, a, M, MR;        // MR = M/2 + 1 reduced bins
   int64_t win_off;             // offset of its window in the window arrays
-  int64_t tw_off;              // offset of its DFT twiddles exp(-2 pi i j / M), j < M/2
+  int64_t tw_off;              // offset of its DFT twiddles exp(-2 pi i j / M), j < M/2, then their
+                               // stage-major copy (M entries in all)
   int64_t gamma_off;           // offset of gamma(k), k = 0..M/2
   int64_t root_off;            // offset of exp(+2 pi i j / M), j < M (update phases)
   uint32_t mr_mul;             // q / MR == (umulhi(q, mr_mul) + q) >> mr_sh, q < 2^31

@@ -370,6 +370,28 @@ __global__ void k_gram_extract(const double2* __restrict__ t, int D, int Mmax, d
   }
 }
 
+// Stage-major copy of the DFT twiddles tw[j] = exp(-2 pi i j / M), j < M/2,
+// stored behind them: entry h - 1 + pos = exp(-2 pi i pos / 2h) =
+// tw[pos M / 2h] for h = 1, 2, 4, ..., M/4 and pos < h, so that the FFT
+// stage with half-length h reads adjacent entries for adjacent pos.
+template <typename T>
+__global__ void k_stage_tw(int M, T* __restrict__ tw) {
+  const int H = M >> 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= H - 1) return;
+  const int h = 1 << (31 - __clz(idx + 1));
+  const int pos = idx + 1 - h;
+  tw[H + idx] = tw[pos * (M / (2 * h))];
+}
+
+hipError_t launch_stage_tw(int M, double2* t64, float2* t32, hipStream_t st) {
+  const int n = M / 2 - 1;
+  if (n <= 0) return hipSuccess;
+  k_stage_tw<double2><<<(n + 255) / 256, 256, 0, st>>>(M, t64);
+  k_stage_tw<float2><<<(n + 255) / 256, 256, 0, st>>>(M, t32);
+  return hipGetLastError();
+}
+
 // Table of M-th roots of unity exp(sign 2 pi i j / M), j = 0..n-1, FP64 and FP32.
 __global__ void k_roots(int M, int n, int sign, double2* __restrict__ o64, float2* __restrict__ o32) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -381,34 +403,42 @@ __global__ void k_roots(int M, int n, int sign, double2* __restrict__ o64, float
 }
 
 // --------------------------------------------------------------------------
-// ||x||^2 per signal in FP64 (Alg. 1 initialisation) and state reset.
+// ||x||^2 per signal in FP64 (Alg. 1 initialisation) and state reset.  Two
+// passes with a fixed summation order: ENERGY_PARTS workgroups per signal
+// each reduce one contiguous chunk, then one wave per signal adds the parts.
 
 template <typename XT>
-__global__ void __launch_bounds__(256) k_energy(const XT* __restrict__ x, const SigDev* __restrict__ sigs,
-                                                SigState* __restrict__ st) {
-  __shared__ double part[256];
-  const int s = blockIdx.x;
+__global__ void __launch_bounds__(256) k_energy_part(const XT* __restrict__ x, const SigDev* __restrict__ sigs,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4];
+  const int s = blockIdx.x, b = blockIdx.y;
   const int64_t L = sigs[s].L, off = sigs[s].x_off;
+  const int64_t chunk = (L + ENERGY_PARTS - 1) / ENERGY_PARTS;
+  const int64_t i0 = b * chunk, i1 = i0 + chunk < L ? i0 + chunk : L;
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < L; i += 256) {
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
     const double v = (double)x[off + i];
     acc += v * v;
   }
-  part[threadIdx.x] = acc;
+  for (int o = 32; o; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-    __syncthreads();
-  }
+  if (threadIdx.x == 0) part[(int64_t)s * ENERGY_PARTS + b] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void __launch_bounds__(64) k_energy_fin(const double* __restrict__ part, SigState* __restrict__ st) {
+  const int s = blockIdx.x;
+  double acc = threadIdx.x < ENERGY_PARTS ? part[(int64_t)s * ENERGY_PARTS + threadIdx.x] : 0.0;
+  for (int o = 32; o; o >>= 1) acc += __shfl_xor(acc, o);
   if (threadIdx.x == 0) {
     SigState z;
-    z.E0 = part[0];
-    z.E = part[0];
+    z.E0 = acc;
+    z.E = acc;
     z.k = 0;
     z.stop = 0;
     z.pad = 0;
     z.updated = z.blocks = z.groups = 0;
-    z.Eout = part[0];
+    z.Eout = acc;
     z.kout = 0;
     z.done = 0;
     z.resets = 0;
@@ -425,9 +455,29 @@ __global__ void __launch_bounds__(256) k_energy(const XT* __restrict__ x, const 
 // z(q) = u(2q) + i u(2q+1) and Z = FFT_H(z),
 //   rho(m) = (Z(m) + conj Z(H-m)) / 2 + e^{-2 pi i m / M} (Z(m) - conj Z(H-m)) / (2i),
 // indices of Z mod H, m = 0..M/2.  One workgroup per frame: bit-reversed load
-// into LDS (H complex entries), radix-2 DIT stages, then the unpacking fused
-// with the plane write and the max-tree leaves (16 bins per leaf).  The signal
-// is zero beyond L and circular over L_padded.
+// into LDS (H complex entries), in-place decimation-in-time stages taken two
+// at a time (a radix-2 pair per thread: 4 entries, 3 twiddles, one barrier;
+// one plain radix-2 stage first when log2 H is odd), then the unpacking fused
+// with the plane write and the max-tree leaves (16 bins per leaf).  LDS entry
+// i lives at slot dgt_sw(i): the low 5 index bits are XOR-ed with a hash of
+// the rest, so the bit-reversed scatter and the butterflies' strided accesses
+// spread over the banks.  The signal is zero beyond L and circular over
+// L_padded.
+
+// Frame of workgroup blockIdx.x: the hardware deals workgroups to the 8 XCDs
+// in turn (workgroup i to XCD i mod 8), so XCD x gets one contiguous run of
+// frames; neighbouring frames share samples (a < gl) and output cache lines
+// in that XCD's L2.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int64_t xcd_frame() {
+  const int64_t i = blockIdx.x, nb = gridDim.x;
+  const int64_t q = nb >> 3, r = nb & 7, x = i & 7;
+  return x * q + (x < r ? x : r) + (i >> 3);
+}
+
+__device__ __forceinline__ int dgt_sw(int i) {
+  const int g = i >> 5;
+  return i ^ (((g ^ (g >> 5) ^ (g >> 10)) * 9) & 31);
+}
 
 template <typename R, typename XT>
 __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const SigDev* __restrict__ sigs,
@@ -439,7 +489,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem_raw);
   const int H = M >> 1, logH = logM - 1;
-  const int64_t f = blockIdx.x;
+  const int64_t f = xcd_frame();
   // signal owning global frame f: last s with frame_prefix[s] <= f
   int lo = 0, hi = batch - 1;
   while (lo < hi) {
@@ -450,43 +500,98 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
   const int s = lo;
   const SigDev& S = sigs[s];
   const int64_t n = f - frame_prefix[s];
-  const int64_t L = S.L, Lp = S.Lp;
+  // 32-bit sample indices (the plan keeps Lp < 2^30)
+  const int L = (int)S.L, Lp = (int)S.Lp;
   const XT* xs = x + S.x_off;
-  for (int q = threadIdx.x; q < H; q += blockDim.x) {
-    R v2[2];
+  // sample of window position tt: (n a + tt) mod Lp = base + tt + gl/2, less
+  // Lp at most once (n a < Lp, and the plan keeps gl <= Lp / 2)
+  int base = (int)n * a - gl / 2;
+  if (base < 0) base += Lp;
+  const int bd = (int)blockDim.x;
+  if (gl <= M) {
+    // at most one window position per slot: two slot pairs per thread in
+    // flight at a time (H / bd = 2 for M <= 1024)
+    for (int q0 = threadIdx.x; q0 < H; q0 += 2 * bd) {
+      R v[2][2];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int i = 2 * q + e;
-      const int t = i < H ? i : i - M;
-      // window samples t, t -+ M, ... inside [-gl/2, gl/2) fold onto slot i
-      R v = (R)0;
-      for (int tt = t - ((t + gl / 2) / M) * M; tt < gl / 2; tt += M) {
-        if (tt < -gl / 2) continue;
-        int64_t l = (n * a + tt) % Lp;
-        if (l < 0) l += Lp;
-        if (l < L) v += (R)xs[l] * win[tt + gl / 2];
+      for (int u = 0; u < 2; ++u) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int i = 2 * (q0 + u * bd) + e;
+          const int t = i < H ? i : i - M;
+          const int tt = t - ((t + gl / 2) >> logM) * M;  // first position >= -gl/2
+          int l = base + (tt + gl / 2);
+          if (l >= Lp) l -= Lp;
+          // unconditional loads (stand-in sample 0 and window entry 0 where
+          // the slot is empty), so that all of them are in flight at once
+          const bool ok = q0 + u * bd < H && tt < gl / 2 && l < L;
+          const R xv = (R)xs[ok ? l : 0], wv = win[ok ? tt + gl / 2 : 0];
+          v[u][e] = ok ? xv * wv : (R)0;
+        }
       }
-      v2[e] = v;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int q = q0 + u * bd;
+        if (q < H) {
+          const int r = logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0;
+          buf[dgt_sw(r)] = Cx<R>{v[u][0], v[u][1]};
+        }
+      }
     }
-    const int r = logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0;
-    buf[r].re = v2[0];
-    buf[r].im = v2[1];
+  } else {
+    for (int q = threadIdx.x; q < H; q += bd) {
+      R v2[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int i = 2 * q + e;
+        const int t = i < H ? i : i - M;
+        // window positions t, t + M, ... in [-gl/2, gl/2) fold onto slot i;
+        // the first is t - floor((t + gl/2) / M) M
+        R v = (R)0;
+        for (int tt = t - ((t + gl / 2) >> logM) * M; tt < gl / 2; tt += M) {
+          int l = base + (tt + gl / 2);
+          if (l >= Lp) l -= Lp;
+          if (l < L) v += (R)xs[l] * win[tt + gl / 2];
+        }
+        v2[e] = v;
+      }
+      const int r = logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0;
+      buf[dgt_sw(r)] = Cx<R>{v2[0], v2[1]};
+    }
   }
   __syncthreads();
-  for (int ls = 1; ls <= logH; ++ls) {
-    const int half = 1 << (ls - 1);
-    const int tstride = 2 * (H >> ls);  // e^{-2 pi i pos / 2^ls} = tw[pos * M / 2^ls]
-    for (int b = threadIdx.x; b < H / 2; b += blockDim.x) {
-      const int grp = b >> (ls - 1);
-      const int pos = b & (half - 1);
-      const int i0 = (grp << ls) + pos, i1 = i0 + half;
-      const Cx<R> wv = tw[pos * tstride];
-      const Cx<R> u = buf[i0], q = buf[i1];
-      const R tr = q.re * wv.re - q.im * wv.im, ti = q.re * wv.im + q.im * wv.re;
-      buf[i0].re = u.re + tr;
-      buf[i0].im = u.im + ti;
-      buf[i1].re = u.re - tr;
-      buf[i1].im = u.im - ti;
+  const Cx<R>* stw = tw + H;  // stage-major twiddles
+  int ls = 1;
+  if (logH & 1) {  // stage 1 alone: twiddle 1
+    for (int b = threadIdx.x; b < H / 2; b += bd) {
+      const int j0 = dgt_sw(2 * b), j1 = dgt_sw(2 * b + 1);
+      const Cx<R> u = buf[j0], q = buf[j1];
+      buf[j0] = Cx<R>{u.re + q.re, u.im + q.im};
+      buf[j1] = Cx<R>{u.re - q.re, u.im - q.im};
+    }
+    __syncthreads();
+    ls = 2;
+  }
+  for (; ls < logH; ls += 2) {
+    // stages ls and ls + 1: sub-transforms of length 2h and 4h, h = 2^(ls-1);
+    // e^{-2 pi i pos / 2h} = stw[h - 1 + pos] (lanes read adjacent entries)
+    const int h = 1 << (ls - 1);
+    for (int b = threadIdx.x; b < H / 4; b += bd) {
+      const int pos = b & (h - 1);
+      const int i0 = ((b >> (ls - 1)) << (ls + 1)) + pos;
+      const int j0 = dgt_sw(i0), j1 = dgt_sw(i0 + h), j2 = dgt_sw(i0 + 2 * h), j3 = dgt_sw(i0 + 3 * h);
+      const Cx<R> wa = stw[h - 1 + pos], wb = stw[2 * h - 1 + pos], wc = stw[3 * h - 1 + pos];
+      const Cx<R> x0 = buf[j0], x1 = buf[j1], x2 = buf[j2], x3 = buf[j3];
+      const R ar = x1.re * wa.re - x1.im * wa.im, ai = x1.re * wa.im + x1.im * wa.re;
+      const R cr = x3.re * wa.re - x3.im * wa.im, ci = x3.re * wa.im + x3.im * wa.re;
+      const Cx<R> y0{x0.re + ar, x0.im + ai}, y1{x0.re - ar, x0.im - ai};
+      const Cx<R> y2{x2.re + cr, x2.im + ci}, y3{x2.re - cr, x2.im - ci};
+      const R br = y2.re * wb.re - y2.im * wb.im, bi = y2.re * wb.im + y2.im * wb.re;
+      const R dr = y3.re * wc.re - y3.im * wc.im, di = y3.re * wc.im + y3.im * wc.re;
+      buf[j0] = Cx<R>{y0.re + br, y0.im + bi};
+      buf[j2] = Cx<R>{y0.re - br, y0.im - bi};
+      buf[j1] = Cx<R>{y1.re + dr, y1.im + di};
+      buf[j3] = Cx<R>{y1.re - dr, y1.im - di};
     }
     __syncthreads();
   }
@@ -497,17 +602,23 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
   Leaf<R>* lf = leaves + S.leaf_base + S.lbase[w] + n * lpf;
   const uint32_t p0 = (uint32_t)(S.off[w] + n * MR);
   const int lane = threadIdx.x & 63;
+  // twiddle of bin m (e^{-2 pi i m / M}; -1 at m = H), fetched one pass ahead
+  auto twid = [&](int m) -> Cx<R> {
+    const Cx<R> t = tw[m < H ? m : 0];  // unconditional load
+    return m < H ? t : Cx<R>{(R)-1, (R)0};
+  };
+  Cx<R> tnext = twid((int)threadIdx.x);
   for (int m0 = 0; m0 < lpf * ROW; m0 += blockDim.x) {
     const int m = m0 + threadIdx.x;
     const bool valid = m < MR;
+    const Cx<R> t = tnext;
+    if (m0 + (int)blockDim.x < lpf * ROW) tnext = twid(m + (int)blockDim.x);
     Cx<R> v = {(R)0, (R)0};
     if (valid) {
-      const Cx<R> zk = buf[m & (H - 1)], zr = buf[(H - m) & (H - 1)];
+      const Cx<R> zk = buf[dgt_sw(m & (H - 1))], zr = buf[dgt_sw((H - m) & (H - 1))];
       // even part (zk + conj zr) / 2, odd part (zk - conj zr) / (2i)
       const R er = (R)0.5 * (zk.re + zr.re), ei = (R)0.5 * (zk.im - zr.im);
       const R or_ = (R)0.5 * (zk.im + zr.im), oi = (R)0.5 * (zr.re - zk.re);
-      Cx<R> t = {(R)-1, (R)0};
-      if (m < H) t = tw[m];
       v.re = er + (t.re * or_ - t.im * oi);
       v.im = ei + (t.re * oi + t.im * or_);
       out[m] = v;
@@ -640,7 +751,7 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
   __shared__ float s_red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int N1p = N1 < 16 ? 16 : N1, N2p = N2 < 16 ? 16 : N2;
-  const int64_t f = blockIdx.x;
+  const int64_t f = xcd_frame();
   int lo = 0, hi = batch - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -653,18 +764,21 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
   const int64_t L = S.L, Lp = S.Lp;
   const XT* xs = x + S.x_off;
   float amax = 0.0f;
+  // (n a + tt) mod Lp = base + tt + gl/2, less Lp at most once (gl <= Lp / 2)
+  int64_t base = (n * a - gl / 2) % Lp;
+  if (base < 0) base += Lp;
+  const int logM = __ffs(M) - 1;
   for (int q = threadIdx.x; q < H; q += blockDim.x) {
     float v2[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int i = 2 * q + e;
       const int t = i < H ? i : i - M;
-      // window samples t, t -+ M, ... inside [-gl/2, gl/2) fold onto slot i
+      // window positions t, t + M, ... in [-gl/2, gl/2) fold onto slot i
       float v = 0.0f;
-      for (int tt = t - ((t + gl / 2) / M) * M; tt < gl / 2; tt += M) {
-        if (tt < -gl / 2) continue;
-        int64_t l = (n * a + tt) % Lp;
-        if (l < 0) l += Lp;
+      for (int tt = t - ((t + gl / 2) >> logM) * M; tt < gl / 2; tt += M) {
+        int64_t l = base + (tt + gl / 2);
+        if (l >= Lp) l -= Lp;
         if (l < L) v += (float)xs[l] * win[tt + gl / 2];
       }
       v2[e] = v;
@@ -2288,12 +2402,16 @@ hipError_t launch_gram_extract(const double2* t, int D, int Mmax, double thr, in
   return hipGetLastError();
 }
 
-hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch, SigState* st_,
+hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch, double* part, SigState* st_,
                          hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  const dim3 grid((unsigned)batch, ENERGY_PARTS);
   if (dtype == 0)
-    k_energy<float><<<batch, 256, 0, st>>>((const float*)x, sigs, st_);
+    k_energy_part<float><<<grid, 256, 0, st>>>((const float*)x, sigs, part);
   else
-    k_energy<double><<<batch, 256, 0, st>>>((const double*)x, sigs, st_);
+    k_energy_part<double><<<grid, 256, 0, st>>>((const double*)x, sigs, part);
+  CHK(hipGetLastError());
+  k_energy_fin<<<batch, 64, 0, st>>>(part, st_);
   return hipGetLastError();
 }
 
@@ -2307,28 +2425,31 @@ hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, in
   const size_t sh = (size_t)(M / 2) * (f64 ? 16 : 8);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
   const dim3 grid((unsigned)frames);
+  // threads per frame: H / 2 (one radix-2 pair per thread, two samples per
+  // thread in the load), clamped to 64 .. 256
+  const int nt = M / 4 < 64 ? 64 : (M / 4 > 256 ? 256 : M / 4);
   const void* kf = f64 ? (dtype == 0 ? (const void*)k_dgt<double, float> : (const void*)k_dgt<double, double>)
                        : (dtype == 0 ? (const void*)k_dgt<float, float> : (const void*)k_dgt<float, double>);
   if (sh > 64 * 1024) CHK(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
   if (f64) {
     if (dtype == 0)
-      k_dgt<double, float><<<grid, 256, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
+      k_dgt<double, float><<<grid, nt, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                   batch, (const double*)win, (const Cx<double>*)tw,
                                                   (Cx<double>*)planes, (Leaf<double>*)leaves,
                                                   (const Cx<double>*)gam, pedantic);
     else
-      k_dgt<double, double><<<grid, 256, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
+      k_dgt<double, double><<<grid, nt, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                    batch, (const double*)win, (const Cx<double>*)tw,
                                                    (Cx<double>*)planes, (Leaf<double>*)leaves,
                                                   (const Cx<double>*)gam, pedantic);
   } else {
     if (dtype == 0)
-      k_dgt<float, float><<<grid, 256, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
+      k_dgt<float, float><<<grid, nt, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                  batch, (const float*)win, (const Cx<float>*)tw,
                                                  (Cx<float>*)planes, (Leaf<float>*)leaves,
                                                  (const Cx<float>*)gam, pedantic);
     else
-      k_dgt<float, double><<<grid, 256, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
+      k_dgt<float, double><<<grid, nt, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
                                                   batch, (const float*)win, (const Cx<float>*)tw,
                                                   (Cx<float>*)planes, (Leaf<float>*)leaves,
                                                  (const Cx<float>*)gam, pedantic);

@@ -65,6 +65,8 @@ def test_kernel_tables_match_oracle(dicts, eps, rel):
     ([(1, 32, 8, 32), (0, 128, 32, 128), (0, 128, 128, 512)], 1024),
     ([(2, 256, 32, 128), (0, 96, 16, 64), (2, 64, 64, 64)], 2048),   # folded windows
     ([(0, 64, 24, 64), (1, 128, 40, 128)], 3000),    # hops dividing neither M: padded to 3840
+    ([(0, 16384, 4096, 16384), (0, 4096, 1024, 4096)], 1 << 16),   # long frames: all FFT stage shapes
+    ([(0, 4, 2, 4), (0, 8, 2, 8), (1, 2, 1, 2)], 64),   # frames of 2, 4 and 8 samples
 ])
 def test_dgt_planes(prec, dicts, L):
     torch = _torch()
@@ -87,6 +89,36 @@ def test_dgt_planes(prec, dicts, L):
     inf = plan.info(0)
     assert inf.L_padded == Lp
     assert abs(inf.E0 - float(xs @ xs)) <= 1e-12 * float(xs @ xs)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dgt_planes_batch(prec):
+    # several signals of different lengths in one launch per system: the
+    # frame -> signal lookup, per-signal energies and padding
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 64, 16, 64), (1, 256, 64, 256), (2, 128, 32, 64)]
+    lens = [3000, 700, 5000, 1024, 2500, 513]
+    rng = np.random.default_rng(77)
+    xs = [rng.standard_normal(L) for L in lens]
+    if prec == "f32":
+        xs = [v.astype(np.float32).astype(np.float64) for v in xs]
+    flags = F64 if prec == "f64" else 0
+    dt = torch.float64 if prec == "f64" else torch.float32
+    plan = mpg.Plan(dicts, lens, 1e-4, flags)
+    plan.analyze(torch.from_numpy(np.concatenate(xs)).to(dt).cuda())
+    tol = 1e-13 if prec == "f64" else 3e-6
+    for s_, (L, v) in enumerate(zip(lens, xs)):
+        Lp = O.padded_length(dicts, L)
+        xp = np.zeros(Lp)
+        xp[:L] = v
+        inf = plan.info(s_)
+        assert inf.L_padded == Lp
+        assert abs(inf.E0 - float(v @ v)) <= 1e-12 * float(v @ v)
+        for w, d in enumerate(dicts):
+            ref = O.dgt(d, xp)
+            got = plan.residual(s_, w).cpu().numpy()
+            assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("fmt,tol", [(0x40, 3e-6), (0x80, 5e-5)])
