@@ -303,7 +303,8 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     if (L[s] <= 0) return MP_E_ARG;
   // the DGT keeps one frame's half-length FFT in LDS
   for (int w = 0; w < W; ++w)
-    if ((size_t)(dicts[w].M / 2) * ((flags & MP_PREC_F64) ? 16 : 8) * (dftf ? 2 : 1) > 160 * 1024)
+    if ((size_t)(dicts[w].M / 2 + (dftf ? dicts[w].M / 2 : dicts[w].M / 64)) * ((flags & MP_PREC_F64) ? 16 : 8) >
+        160 * 1024)
       return MP_E_LIMIT;
   {
     // padded lengths must fit every pair's kernel (checked before any HIP call)

@@ -459,10 +459,10 @@ __global__ void __launch_bounds__(64) k_energy_fin(const double* __restrict__ pa
 // at a time (a radix-2 pair per thread: 4 entries, 3 twiddles, one barrier;
 // one plain radix-2 stage first when log2 H is odd), then the unpacking fused
 // with the plane write and the max-tree leaves (16 bins per leaf).  LDS entry
-// i lives at slot dgt_sw(i): the low 5 index bits are XOR-ed with a hash of
-// the rest, so the bit-reversed scatter and the butterflies' strided accesses
-// spread over the banks.  The signal is zero beyond L and circular over
-// L_padded.
+// i lives at slot dgt_sw(i) = i + i/32 (one pad entry per 32), which spreads
+// the bit-reversed scatter and most butterfly strides over the banks at two
+// VALU operations per address (the kernel is bound by VALU issue).  The
+// signal is zero beyond L and circular over L_padded.
 
 // Frame of workgroup blockIdx.x: the hardware deals workgroups to the 8 XCDs
 // in turn (workgroup i to XCD i mod 8), so XCD x gets one contiguous run of
@@ -474,10 +474,7 @@ __device__ __forceinline__ int64_t xcd_frame() {
   return x * q + (x < r ? x : r) + (i >> 3);
 }
 
-__device__ __forceinline__ int dgt_sw(int i) {
-  const int g = i >> 5;
-  return i ^ (((g ^ (g >> 5) ^ (g >> 10)) * 9) & 31);
-}
+__device__ __forceinline__ int dgt_sw(int i) { return i + (i >> 5); }
 
 template <typename R, typename XT>
 __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const SigDev* __restrict__ sigs,
@@ -525,7 +522,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
           // unconditional loads (stand-in sample 0 and window entry 0 where
           // the slot is empty), so that all of them are in flight at once
           const bool ok = q0 + u * bd < H && tt < gl / 2 && l < L;
-          const R xv = (R)xs[ok ? l : 0], wv = win[ok ? tt + gl / 2 : 0];
+          const R xv = (R)xs[ok ? (uint32_t)l : 0u], wv = win[ok ? (uint32_t)(tt + gl / 2) : 0u];
           v[u][e] = ok ? xv * wv : (R)0;
         }
       }
@@ -580,7 +577,8 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
       const int pos = b & (h - 1);
       const int i0 = ((b >> (ls - 1)) << (ls + 1)) + pos;
       const int j0 = dgt_sw(i0), j1 = dgt_sw(i0 + h), j2 = dgt_sw(i0 + 2 * h), j3 = dgt_sw(i0 + 3 * h);
-      const Cx<R> wa = stw[h - 1 + pos], wb = stw[2 * h - 1 + pos], wc = stw[3 * h - 1 + pos];
+      const Cx<R> wa = stw[(uint32_t)(h - 1 + pos)], wb = stw[(uint32_t)(2 * h - 1 + pos)],
+                  wc = stw[(uint32_t)(3 * h - 1 + pos)];
       const Cx<R> x0 = buf[j0], x1 = buf[j1], x2 = buf[j2], x3 = buf[j3];
       const R ar = x1.re * wa.re - x1.im * wa.im, ai = x1.re * wa.im + x1.im * wa.re;
       const R cr = x3.re * wa.re - x3.im * wa.im, ci = x3.re * wa.im + x3.im * wa.re;
@@ -604,7 +602,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
   const int lane = threadIdx.x & 63;
   // twiddle of bin m (e^{-2 pi i m / M}; -1 at m = H), fetched one pass ahead
   auto twid = [&](int m) -> Cx<R> {
-    const Cx<R> t = tw[m < H ? m : 0];  // unconditional load
+    const Cx<R> t = tw[m < H ? (uint32_t)m : 0u];  // unconditional load
     return m < H ? t : Cx<R>{(R)-1, (R)0};
   };
   Cx<R> tnext = twid((int)threadIdx.x);
@@ -621,7 +619,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
       const R or_ = (R)0.5 * (zk.im + zr.im), oi = (R)0.5 * (zr.re - zk.re);
       v.re = er + (t.re * or_ - t.im * oi);
       v.im = ei + (t.re * oi + t.im * or_);
-      out[m] = v;
+      out[(uint32_t)m] = v;
     }
     const bool ped = pedantic && valid && m != 0 && m != H;
     const R val = sel_score<R>(v.re, v.im, ped ? gam[m] : Cx<R>{(R)0, (R)0}, ped);
@@ -630,7 +628,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
     const uint64_t bal = __ballot(valid && bits == rm);
     const uint32_t rowbits = (uint32_t)(bal >> (lane & ~(ROW - 1))) & 0xFFFFu;
     if (rowbits && lane == (lane & ~(ROW - 1)) + __ffs(rowbits) - 1)
-      lf[m >> LOG_ROW] = make_leaf(KeyOps<R>::make(val, p0 + (uint32_t)m), v.re, v.im);
+      lf[(uint32_t)m >> LOG_ROW] = make_leaf(KeyOps<R>::make(val, p0 + (uint32_t)m), v.re, v.im);
   }
 }
 
@@ -2422,7 +2420,7 @@ hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, in
   if (frames <= 0) return hipSuccess;
   int logM = 0;
   while ((1 << logM) < M) ++logM;
-  const size_t sh = (size_t)(M / 2) * (f64 ? 16 : 8);
+  const size_t sh = (size_t)(M / 2 + M / 64) * (f64 ? 16 : 8);  // H entries + one pad per 32
   if (sh > 160 * 1024) return hipErrorInvalidValue;
   const dim3 grid((unsigned)frames);
   // threads per frame: H / 2 (one radix-2 pair per thread, two samples per
