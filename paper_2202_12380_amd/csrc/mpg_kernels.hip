@@ -747,7 +747,7 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
   Cx<float>* buf = reinterpret_cast<Cx<float>*>(smem_raw);  // z, then B
   Cx<float>* ybuf = buf + H;                                  // Z
   __shared__ float s_red[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
   const int N1p = N1 < 16 ? 16 : N1, N2p = N2 < 16 ? 16 : N2;
   const int64_t f = xcd_frame();
   int lo = 0, hi = batch - 1;
@@ -774,10 +774,19 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
       const int t = i < H ? i : i - M;
       // window positions t, t + M, ... in [-gl/2, gl/2) fold onto slot i
       float v = 0.0f;
-      for (int tt = t - ((t + gl / 2) >> logM) * M; tt < gl / 2; tt += M) {
+      if (gl <= M) {  // at most one position: unconditional loads (stand-ins where none)
+        const int tt = t - ((t + gl / 2) >> logM) * M;
         int64_t l = base + (tt + gl / 2);
         if (l >= Lp) l -= Lp;
-        if (l < L) v += (float)xs[l] * win[tt + gl / 2];
+        const bool ok = tt < gl / 2 && l < L;
+        const float xv = (float)xs[ok ? l : 0], wv = win[ok ? tt + gl / 2 : 0];
+        v = ok ? xv * wv : 0.0f;
+      } else {
+        for (int tt = t - ((t + gl / 2) >> logM) * M; tt < gl / 2; tt += M) {
+          int64_t l = base + (tt + gl / 2);
+          if (l >= Lp) l -= Lp;
+          if (l < L) v += (float)xs[l] * win[tt + gl / 2];
+        }
       }
       v2[e] = v;
     }
@@ -789,14 +798,15 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
   for (int o = 32; o; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
   if (lane == 0) s_red[wave] = amax;
   __syncthreads();
-  amax = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+  amax = s_red[0];
+  for (int v = 1; v < nw; ++v) amax = fmaxf(amax, s_red[v]);
   int ex = 0;
   if (amax > 0.0f) frexpf(amax, &ex);
   const float scale = ldexpf(1.0f, -ex), unscale = ldexpf(1.0f, ex);
 
   // ---- step 1: B = X F_N2 (row blocks of 16 n1), twiddle, in place ----
   const int r16 = lane & 15, k4 = (lane >> 4) * 4;
-  for (int rb = wave; rb < (N1p >> 4); rb += 4) {
+  for (int rb = wave; rb < (N1p >> 4); rb += nw) {
     const int n1a = 16 * rb + r16;  // A-operand row of this lane
     mf_s4 xr_h[8], xr_l[8], xi_h[8], xi_l[8];
 #pragma unroll
@@ -853,7 +863,7 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
   __syncthreads();
 
   // ---- step 2: Z = F_N1 B (column blocks of 16 k2) ----
-  for (int ct = wave; ct < (N2p >> 4); ct += 4) {
+  for (int ct = wave; ct < (N2p >> 4); ct += nw) {
     const int k2b = 16 * ct + r16;  // B-operand column of this lane
     mf_s4 br_h[8], br_l[8], bi_h[8], bi_l[8];
 #pragma unroll
@@ -2472,6 +2482,9 @@ hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs
   const size_t sh = (size_t)M * 8;  // z / B and Z, H complex FP32 each
   if (sh > 160 * 1024) return hipErrorInvalidValue;
   const dim3 grid((unsigned)frames);
+  // one wave per 16-row block of the larger GEMM dimension (1 to 4 waves)
+  const int tiles = (N1 > N2 ? N1 : N2) / 16;
+  const int nt = 64 * (tiles < 1 ? 1 : (tiles > 4 ? 4 : tiles));
   const Cx<float>* twc = (const Cx<float>*)tw;
   Cx<float>* pl = (Cx<float>*)planes;
   Leaf<float>* lv = (Leaf<float>*)leaves;
@@ -2480,7 +2493,7 @@ hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs
     if (sh > 64 * 1024)                                                                                     \
       CHK(hipFuncSetAttribute((const void*)k_dgt_mfma<F, XT>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
                               (int)sh));                                                                    \
-    k_dgt_mfma<F, XT><<<grid, 256, sh, st>>>((const XT*)x, sigs, w, gl, a, M, MR, frame_prefix, batch, win,  \
+    k_dgt_mfma<F, XT><<<grid, nt, sh, st>>>((const XT*)x, sigs, w, gl, a, M, MR, frame_prefix, batch, win,   \
                                              twc, N1, N2, F1, F2, pl, lv, (const Cx<float>*)gam, pedantic); \
   } while (0)
   if (fmt == 0) {
