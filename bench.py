@@ -62,7 +62,21 @@ def cpu_baseline(wl, xs, sample_idx, workers):
                             "processes, %.1f s wall, %.1f s CPU" % (
                                 ",".join(map(str, sample_idx)), int(sum(len(xs[i]) for i in sample_idx)),
                                 atoms, workers, wall, cpu_s),
-                     per_core=atoms / cpu_s)
+                     per_core=atoms / cpu_s, host=_host_info())
+
+
+def _host_info():
+    """CPU model and logical CPU count of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
 def main():
