@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--plan-flags", type=lambda v: int(v, 0), default=0,
                     help="extra plan flags (e.g. 0x100: pedantic selection, 0x20: conjugate partner only "
                          "when gamma != 0, 0x40 / 0x80: split FP16 / BF16 DFT)")
+    ap.add_argument("--probe-atoms", type=int, default=2000,
+                    help="selections per signal in each autotuner probe (0: default schedule, no autotuning)")
     ap.add_argument("--eps", type=float, action="append", default=None,
                     help="restrict --study noise to these thresholds")
     ap.add_argument("--study", choices=["precision", "noise"], default=None,
@@ -142,9 +144,15 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 
-    # ---- batched FP32 path ----
-    plan = mpg.Plan(wl.dicts, lengths, wl.eps, args.plan_flags)
+    # ---- batched FP32 path: schedule chosen by the autotuner (untimed, like plan creation) ----
     x = torch.from_numpy(np.concatenate(xs).astype(np.float32)).to(dev)
+    tune = None
+    if args.probe_atoms > 0 and not (args.plan_flags & (mpg.MP_SCHED_NT512 | mpg.MP_SCHED_G128)):
+        plan, tune = mpg.Plan.autotuned(wl.dicts, lengths, x, wl.eps, args.plan_flags,
+                                        probe_atoms=args.probe_atoms, stream=stream)
+        log("autotuned: %s" % tune)
+    else:
+        plan = mpg.Plan(wl.dicts, lengths, wl.eps, args.plan_flags)
     log("plan built; warmup")
     for _ in range(args.warmup):
         plan.analyze(x, stream)
@@ -268,6 +276,7 @@ def main():
             "stop_reasons": {"K": stops[1], "snr": stops[2], "E<0": stops[3], "zero": stops[4]},
             "min_snr_db": float(min(snr_reached)),
             "plan_flags": args.plan_flags,
+            "schedule": {"threads": int(st.threads), "group_leaves": int(st.group_leaves), "autotune": tune},
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,

@@ -74,6 +74,12 @@ extern "C" {
  * Eq. dualatprod) instead of the largest |rho|^2; DC and Nyquist atoms, which
  * have no partner, score |rho|^2. */
 #define MP_PEDANTIC 0x100u
+/* Schedule of the FP32 MP kernel (FP32 plans only).  Default: 768 threads
+ * (12 waves) per signal and 256-leaf tree groups, each falling back when the
+ * tree groups would not fit the LDS.  The results do not depend on the
+ * schedule; mp_autotune picks one by timing. */
+#define MP_SCHED_NT512 0x1000u   /* 512 threads (8 waves) per signal            */
+#define MP_SCHED_G128 0x2000u    /* 128-leaf tree groups                        */
 
 /* ---- input sample types for mp_analyze / output types for mp_resynth ---- */
 #define MP_DTYPE_F32 0
@@ -143,7 +149,7 @@ typedef struct {
  * 4.2; threshold Eq. truncgram, absolute unless MP_THR_REL) plus FP32 copies.
  * kernel_tol is the threshold epsilon (> 0).  flags: MP_PREC_*, MP_THR_REL,
  * MP_CONJ_GATE_GAMMA, MP_PEDANTIC, at most one MP_DFT_* (not with
- * MP_PREC_F64).  Uses the
+ * MP_PREC_F64), MP_SCHED_* (not with MP_PREC_F64).  Uses the
  * current HIP device; blocks until the kernels are built.  *out receives the
  * plan.  MP_E_LIMIT: a frame's FFT exceeds the LDS of one workgroup (M/2
  * complex entries; twice that for MP_DFT_*), or the signal's tree groups do
@@ -151,6 +157,34 @@ typedef struct {
 int mp_plan_create(const mp_dict *dicts, int32_t W, const int64_t *L,
                    int32_t batch, double kernel_tol, uint32_t flags,
                    mp_plan **out);
+
+/* Timings of mp_autotune: one entry per schedule tried. */
+typedef struct {
+  int32_t n_cand;          /* schedules tried (distinct launch shapes)       */
+  int32_t chosen;          /* index of the returned one                       */
+  uint32_t flags[4];       /* MP_SCHED_* bits of each                         */
+  int32_t threads[4];      /* threads per workgroup of each                   */
+  int32_t group_leaves[4]; /* leaves per tree group of each                   */
+  double probe_ms[4];      /* device time of each probe run                   */
+} mp_tune_report;
+
+/* Schedule autotuner (no counterpart in the paper: the launch shape of the
+ * batched loop is a property of this GPU implementation).  Creates a plan as
+ * mp_plan_create(dicts, W, L, batch, kernel_tol, flags | s) for each
+ * schedule s among MP_SCHED_* combinations (one schedule for FP64 plans),
+ * skips schedules whose plan would duplicate an earlier launch shape or does
+ * not fit (MP_E_LIMIT), analyses x_dev (as mp_analyze) and times an mp_run of
+ * probe_atoms selections per signal without SNR rule on `stream` (device
+ * events; synchronizes).  *out receives the fastest plan, the others are
+ * destroyed; the returned plan holds the probe's state, so call mp_analyze
+ * before using it.  rep (may be null) receives the timings.  Errors:
+ * MP_E_ARG for null pointers, probe_atoms <= 0 or MP_SCHED_* bits in flags,
+ * else those of mp_plan_create, mp_analyze and mp_run (no plan is returned
+ * then). */
+int mp_autotune(const mp_dict *dicts, int32_t W, const int64_t *L,
+                int32_t batch, double kernel_tol, uint32_t flags,
+                const void *x_dev, int32_t dtype, int64_t probe_atoms,
+                hipStream_t stream, mp_plan **out, mp_tune_report *rep);
 
 /* Analysis: E0 = ||x||^2 (FP64), rho_0 = D_w* x for every system (Sec. 5)
  * and the max tree over |rho_0|^2 (Sec. 5.1).  x_dev holds the batch packed

@@ -293,10 +293,12 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
   *out = nullptr;
   if (!dicts || !L || W < 1 || W > MAXW || batch < 1 || batch > (1 << 20)) return MP_E_ARG;
   if (!(kernel_tol >= 0.0 && kernel_tol < 1.0)) return MP_E_ARG;
-  if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA | MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT | MP_PEDANTIC))
+  if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA | MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT | MP_PEDANTIC |
+                MP_SCHED_NT512 | MP_SCHED_G128))
     return MP_E_ARG;
   const uint32_t dftf = flags & (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT);
   if (dftf == (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT) || (dftf && (flags & MP_PREC_F64))) return MP_E_ARG;
+  if ((flags & MP_PREC_F64) && (flags & (MP_SCHED_NT512 | MP_SCHED_G128))) return MP_E_ARG;
   int rc = check_dicts(dicts, W);
   if (rc) return rc;
   for (int s = 0; s < batch; ++s)
@@ -388,7 +390,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
         // 768 threads (12 waves) unless the group keys and the owners'
         // scratch only fit the LDS with 512 (or MPG_NT=512 asks for it)
         p->G = 0;
-        int gpref = 256, ntpref = 768;
+        int gpref = (flags & MP_SCHED_G128) ? 128 : 256, ntpref = (flags & MP_SCHED_NT512) ? 512 : 768;
         if (const char* e = getenv("MPG_GL"))
           if (atoi(e) == 128) gpref = 128;
         if (const char* e = getenv("MPG_NT"))
@@ -784,6 +786,63 @@ fail:
   hipFree(d_max);
   free_plan(p);
   return rc;
+}
+
+int mp_autotune(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t batch, double kernel_tol, uint32_t flags,
+                const void* x_dev, int32_t dtype, int64_t probe_atoms, hipStream_t stream, mp_plan** out,
+                mp_tune_report* rep) {
+  if (!out || !x_dev || probe_atoms <= 0 || (flags & (MP_SCHED_NT512 | MP_SCHED_G128))) return MP_E_ARG;
+  *out = nullptr;
+  const uint32_t cands[4] = {0u, MP_SCHED_G128, MP_SCHED_NT512, MP_SCHED_NT512 | MP_SCHED_G128};
+  const int ncand = (flags & MP_PREC_F64) ? 1 : 4;
+  mp_tune_report r;
+  memset(&r, 0, sizeof(r));
+  r.chosen = -1;
+  mp_plan* best = nullptr;
+  double best_ms = 0.0;
+  for (int c = 0; c < ncand; ++c) {
+    mp_plan* p = nullptr;
+    int rc = mp_plan_create(dicts, W, L, batch, kernel_tol, flags | cands[c], &p);
+    if (rc == MP_E_LIMIT) continue;  // this schedule does not fit
+    if (rc != MP_OK) {
+      mp_plan_destroy(best);
+      return rc;
+    }
+    bool dup = false;  // a preference that fell back to an earlier launch shape
+    for (int i = 0; i < r.n_cand; ++i)
+      if (r.threads[i] == p->nt && r.group_leaves[i] == p->G) dup = true;
+    if (dup) {
+      mp_plan_destroy(p);
+      continue;
+    }
+    rc = mp_analyze(p, x_dev, dtype, stream);
+    if (rc == MP_OK) rc = mp_run(p, probe_atoms, 0.0, stream);
+    if (rc == MP_OK && hipStreamSynchronize(stream) != hipSuccess) rc = MP_E_HIP;
+    mp_stats st;
+    if (rc == MP_OK) rc = mp_get_stats(p, &st);
+    if (rc != MP_OK) {
+      mp_plan_destroy(p);
+      mp_plan_destroy(best);
+      return rc;
+    }
+    const int i = r.n_cand++;
+    r.flags[i] = cands[c];
+    r.threads[i] = p->nt;
+    r.group_leaves[i] = p->G;
+    r.probe_ms[i] = st.loop_ms;
+    if (!best || st.loop_ms < best_ms) {
+      mp_plan_destroy(best);
+      best = p;
+      best_ms = st.loop_ms;
+      r.chosen = i;
+    } else {
+      mp_plan_destroy(p);
+    }
+  }
+  if (!best) return MP_E_LIMIT;
+  *out = best;
+  if (rep) *rep = r;
+  return MP_OK;
 }
 
 int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream) {

@@ -21,6 +21,7 @@ MP_PREC_F32, MP_PREC_F64 = 0x0, 0x1
 MP_THR_REL, MP_CONJ_GATE_GAMMA = 0x10, 0x20
 MP_DFT_F16SPLIT, MP_DFT_BF16SPLIT = 0x40, 0x80
 MP_PEDANTIC = 0x100
+MP_SCHED_NT512, MP_SCHED_G128 = 0x1000, 0x2000
 MP_DTYPE_F32, MP_DTYPE_F64 = 0, 1
 MP_STOP_NONE, MP_STOP_K, MP_STOP_SNR, MP_STOP_ENEG, MP_STOP_ZERO = range(5)
 
@@ -50,6 +51,18 @@ class mp_kernel_info(C.Structure):
                 ("n_nonzero", C.c_int64)]
 
 
+class mp_tune_report(C.Structure):
+    _fields_ = [("n_cand", C.c_int32), ("chosen", C.c_int32), ("flags", C.c_uint32 * 4),
+                ("threads", C.c_int32 * 4), ("group_leaves", C.c_int32 * 4), ("probe_ms", C.c_double * 4)]
+
+    def as_dict(self):
+        n = self.n_cand
+        return {"chosen": self.chosen,
+                "schedules": [{"flags": int(self.flags[i]), "threads": int(self.threads[i]),
+                               "group_leaves": int(self.group_leaves[i]), "probe_ms": float(self.probe_ms[i])}
+                              for i in range(n)]}
+
+
 class mp_stats(C.Structure):
     _fields_ = [("atoms", C.c_int64), ("updated", C.c_int64), ("blocks", C.c_int64),
                 ("l1_groups", C.c_int64), ("loop_ms", C.c_double), ("analyze_ms", C.c_double),
@@ -59,7 +72,7 @@ class mp_stats(C.Structure):
 EXPORTS = ["mp_plan_create", "mp_analyze", "mp_run", "mp_run_resets", "mp_get_atoms", "mp_get_energy",
            "mp_get_coefs", "mp_get_residual", "mp_resynth", "mp_signal_info_get",
            "mp_kernel_info_get", "mp_get_kernel", "mp_get_stats", "mp_plan_destroy",
-           "mp_strerror"]
+           "mp_autotune", "mp_strerror"]
 
 _lib = None
 
@@ -76,6 +89,8 @@ def lib():
     L.mp_plan_create.argtypes = [C.POINTER(mp_dict), i32, C.POINTER(C.c_int64), i32, dbl, C.c_uint32,
                                  C.POINTER(vp)]
     L.mp_analyze.argtypes = [vp, vp, i32, vp]
+    L.mp_autotune.argtypes = [C.POINTER(mp_dict), i32, C.POINTER(C.c_int64), i32, dbl, C.c_uint32, vp, i32, i64,
+                              vp, C.POINTER(vp), C.POINTER(mp_tune_report)]
     L.mp_run.argtypes = [vp, i64, dbl, vp]
     L.mp_run_resets.argtypes = [vp, vp, i32, i64, dbl, i64, dbl, vp]
     L.mp_get_atoms.argtypes = [vp, i32, vp, i64, C.POINTER(C.c_int64)]
@@ -127,6 +142,19 @@ def mp_plan_create(dicts: Sequence[Sequence[int]], lengths: Sequence[int], kerne
     _chk(lib().mp_plan_create(arr, W, Ls, len(lengths), float(kernel_tol), int(flags), C.byref(out)),
          "mp_plan_create")
     return out.value
+
+
+def mp_autotune(dicts: Sequence[Sequence[int]], lengths: Sequence[int], kernel_tol: float, flags: int,
+                x_ptr: int, dtype: int, probe_atoms: int, stream=None):
+    """Returns (plan handle, mp_tune_report)."""
+    W = len(dicts)
+    arr = (mp_dict * W)(*[mp_dict(*map(int, d)) for d in dicts])
+    Ls = (C.c_int64 * len(lengths))(*map(int, lengths))
+    out = C.c_void_p()
+    rep = mp_tune_report()
+    _chk(lib().mp_autotune(arr, W, Ls, len(lengths), float(kernel_tol), int(flags), x_ptr, int(dtype),
+                           int(probe_atoms), _stream(stream), C.byref(out), C.byref(rep)), "mp_autotune")
+    return out.value, rep
 
 
 def mp_analyze(plan: int, x_ptr: int, dtype: int, stream=None):
@@ -211,12 +239,22 @@ def mp_plan_destroy(plan: int):
 class Plan:
     """Owns one mp_plan; torch supplies device memory and the stream."""
 
-    def __init__(self, dicts, lengths, kernel_tol=1e-4, flags=0):
+    def __init__(self, dicts, lengths, kernel_tol=1e-4, flags=0, _handle=None):
         self.dicts = [tuple(map(int, d)) for d in dicts]
         self.lengths = [int(L) for L in lengths]
         self.flags = flags
         self.f64 = bool(flags & MP_PREC_F64)
-        self.h = mp_plan_create(self.dicts, self.lengths, kernel_tol, flags)
+        self.h = _handle if _handle is not None else mp_plan_create(self.dicts, self.lengths, kernel_tol, flags)
+
+    @classmethod
+    def autotuned(cls, dicts, lengths, x, kernel_tol=1e-4, flags=0, probe_atoms=2000, stream=None):
+        """The fastest schedule for this batch (mp_autotune); returns (plan, report dict).
+        The plan must be analysed again before use."""
+        import torch
+        assert x.is_cuda and x.is_contiguous() and x.dim() == 1
+        dt = MP_DTYPE_F32 if x.dtype == torch.float32 else MP_DTYPE_F64
+        h, rep = mp_autotune(dicts, lengths, kernel_tol, flags, x.data_ptr(), dt, probe_atoms, stream)
+        return cls(dicts, lengths, kernel_tol, flags, _handle=h), rep.as_dict()
 
     def close(self):
         if self.h:

@@ -48,6 +48,8 @@ def test_strerror_and_argument_errors_without_gpu():
         ([(0, 32768, 8192, 32768)], [65536], 1e-4, 0x40, mpg.MP_E_LIMIT),       # split DFT frame exceeds LDS
         ([(0, 64, 16, 64)], [1024], 1e-4, 0x41, mpg.MP_E_ARG),                  # split DFT with FP64
         ([(0, 64, 16, 64)], [1024], 1e-4, 0xC0, mpg.MP_E_ARG),                  # two DFT formats
+        ([(0, 64, 16, 64)], [1024], 1e-4, 0x1001, mpg.MP_E_ARG),                # FP32 schedule on an FP64 plan
+        ([(0, 64, 16, 64)], [1024], 1e-4, 0x4000, mpg.MP_E_ARG),                # unknown schedule bit
     ]
     for dicts, lens, eps, flags, code in cases:
         with pytest.raises(mpg.MPError) as e:
@@ -57,6 +59,18 @@ def test_strerror_and_argument_errors_without_gpu():
     assert L.mp_plan_destroy(None) == mpg.MP_E_ARG
     assert L.mp_run(None, 0, 0.0, None) == mpg.MP_E_ARG
     assert L.mp_run_resets(None, None, 0, 0, 0.0, 1, 0.0, None) == mpg.MP_E_ARG
+    # autotuner: bad arguments are rejected before any plan is made
+    import ctypes as C
+    arr = (mpg.mp_dict * 1)(mpg.mp_dict(0, 64, 16, 64))
+    Ls = (C.c_int64 * 1)(1024)
+    out = C.c_void_p()
+    fake_x = C.c_void_p(16)  # never dereferenced: every case fails validation first
+    assert L.mp_autotune(arr, 1, Ls, 1, 1e-4, 0, fake_x, 0, 100, None, None, None) == mpg.MP_E_ARG
+    assert L.mp_autotune(arr, 1, Ls, 1, 1e-4, 0, None, 0, 100, None, C.byref(out), None) == mpg.MP_E_ARG
+    assert L.mp_autotune(arr, 1, Ls, 1, 1e-4, 0, fake_x, 0, 0, None, C.byref(out), None) == mpg.MP_E_ARG
+    assert L.mp_autotune(arr, 1, Ls, 1, 1e-4, mpg.MP_SCHED_NT512, fake_x, 0, 100, None, C.byref(out),
+                         None) == mpg.MP_E_ARG
+    assert out.value is None
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

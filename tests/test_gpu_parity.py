@@ -275,6 +275,41 @@ def test_mp_fp32_launch_shapes(env, threads, groups, monkeypatch):
         assert_tolerance(ga[i], orc)
 
 
+def test_mp_fp32_schedules_identical_and_autotune():
+    # every FP32 schedule (threads per signal, leaves per tree group) gives the
+    # same atoms bit for bit; the autotuner returns one of them, usable after a
+    # fresh analysis
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)]
+    lens = [16384, 9000, 12345]
+    xs = [S.audio_like(L, S.rng(81, i)).astype(np.float32) for i, L in enumerate(lens)]
+    runs = {}
+    for f in (0, mpg.MP_SCHED_G128, mpg.MP_SCHED_NT512, mpg.MP_SCHED_NT512 | mpg.MP_SCHED_G128):
+        plan, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=f)
+        st = plan.stats()
+        runs[(st.threads, st.group_leaves)] = ga
+    assert set(runs) == {(768, 256), (768, 128), (512, 256), (512, 128)}
+    ref = runs[(768, 256)]
+    for shape, ga in runs.items():
+        for a, b in zip(ga, ref):
+            assert len(a) == len(b), shape
+            assert np.array_equal(a, b), shape
+    x = torch.from_numpy(np.concatenate(xs)).cuda()
+    plan, rep = mpg.Plan.autotuned(dicts, lens, x, 1e-4, 0, probe_atoms=300)
+    assert 1 <= len(rep["schedules"]) <= 4 and 0 <= rep["chosen"] < len(rep["schedules"])
+    assert all(s["probe_ms"] > 0 for s in rep["schedules"])
+    st = plan.stats()
+    ch = rep["schedules"][rep["chosen"]]
+    assert (st.threads, st.group_leaves) == (ch["threads"], ch["group_leaves"])
+    assert all(len(plan.atoms(s)) == 300 for s in range(len(lens)))  # the probe's state
+    plan.analyze(x)
+    plan.run(0, 25.0)
+    torch.cuda.synchronize()
+    for s in range(len(lens)):
+        assert np.array_equal(plan.atoms(s), ref[s])
+
+
 def test_mp_fp32_batch_ragged():
     _torch()
     dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)]
