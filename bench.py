@@ -187,7 +187,8 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_source_sha") == _kernel_sha():
+        if tr.get("kernel_source_sha") == _kernel_sha() and tr.get("kernel") == "mpg::k_mp32<%d, 2, %d>" % (
+                st.threads, st.group_leaves):
             traffic = tr.get("bytes_per_launch")
     coefs = sum(int(i.n_coefs) for i in infos)
     dgt_bytes = 4.0 * sum(lengths) * len(wl.dicts) + 8.0 * coefs
@@ -225,6 +226,7 @@ def main():
     fp64 = None
     if args.fp64_sample > 0:
         tot_atoms, tot_ms = 0, 0.0
+        same64, gap64 = [], []
         for i in range(min(args.fp64_sample, len(xs))):
             p64 = mpg.Plan(wl.dicts, [lengths[i]], wl.eps, mpg.MP_PREC_F64)
             x64 = torch.from_numpy(xs[i].astype(np.float64)).to(dev)
@@ -236,9 +238,17 @@ def main():
             torch.cuda.synchronize()
             tot_ms += a.elapsed_time(b)
             tot_atoms += int(p64.info(0).n_atoms)
+            if i in orc:  # the same input as the oracle's: the sequence must be identical
+                ga, r = p64.atoms(0), orc[i]
+                same64.append(len(ga) == r["n_atoms"] and bool(np.all(
+                    (ga["w"] == r["w"]) & (ga["m"] == r["m"]) & (ga["n"] == r["n"]))))
+                gap64.append(float(np.min(r["gap"][:r["n_atoms"]])) if r["n_atoms"] else None)
             p64.close()
         fp64 = dict(atoms_per_s=tot_atoms / (tot_ms * 1e-3), signals=min(args.fp64_sample, len(xs)),
-                    atoms=tot_atoms, loop_ms=tot_ms)
+                    atoms=tot_atoms, loop_ms=tot_ms,
+                    identical_to_oracle=same64 if same64 else None,
+                    smallest_top2_gap=min(g for g in gap64 if g is not None) if any(
+                        g is not None for g in gap64) else None)
 
     # ---- a plain device copy of 512 MiB for scale: the HBM rate a streaming kernel reaches ----
     src = torch.empty(1 << 27, dtype=torch.float32, device=dev)

@@ -175,7 +175,10 @@ typedef struct {
  * skips schedules whose plan would duplicate an earlier launch shape or does
  * not fit (MP_E_LIMIT), analyses x_dev (as mp_analyze) and times an mp_run of
  * probe_atoms selections per signal without SNR rule on `stream` (device
- * events; synchronizes).  *out receives the fastest plan, the others are
+ * events; synchronizes).  The schedules are tried in the order default,
+ * MP_SCHED_G128, MP_SCHED_NT512, both; a later one replaces the current
+ * choice only when its probe is more than 1 % faster, so that timing noise
+ * does not flip the choice.  *out receives the chosen plan, the others are
  * destroyed; the returned plan holds the probe's state, so call mp_analyze
  * before using it.  rep (may be null) receives the timings.  Errors:
  * MP_E_ARG for null pointers, probe_atoms <= 0 or MP_SCHED_* bits in flags,

@@ -830,7 +830,7 @@ int mp_autotune(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t batch
     r.threads[i] = p->nt;
     r.group_leaves[i] = p->G;
     r.probe_ms[i] = st.loop_ms;
-    if (!best || st.loop_ms < best_ms) {
+    if (!best || st.loop_ms < 0.99 * best_ms) {  // more than 1 % faster: noise does not flip the choice
       mp_plan_destroy(best);
       best = p;
       best_ms = st.loop_ms;
