@@ -346,7 +346,8 @@ def precision_study(args):
     x32 = torch.from_numpy(np.concatenate(xs).astype(np.float32)).to(dev)
     stream = torch.cuda.current_stream().cuda_stream
     formats = (("fp16 pairs (MFMA)", mpg.MP_DFT_F16SPLIT), ("bf16 pairs (MFMA)", mpg.MP_DFT_BF16SPLIT),
-               ("fp32 (FFT)", 0), ("fp64 (FFT, FP64 loop)", mpg.MP_PREC_F64))
+               ("fp32 (FFT)", 0), ("fp64 (FFT), FP32 loop", mpg.MP_DFT_F64),
+               ("fp64 (FFT, FP64 loop)", mpg.MP_PREC_F64))
     for e in eps_list:
         for name, flags in formats:
             plan = mpg.Plan(wl.dicts, lengths, e, flags)

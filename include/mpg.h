@@ -63,10 +63,14 @@ extern "C" {
 #define MP_PREC_F64 0x1u         /* FP64 planes, kernels and updates               */
 #define MP_THR_REL 0x10u         /* threshold relative to each kernel's peak |h|   */
 #define MP_CONJ_GATE_GAMMA 0x20u /* conjugate-partner update only when gamma != 0  */
-/* DFT inside the analysis (FP32 plans only; default: FP32 radix-2 FFT).  The
- * split variants run the DFT on matrix cores as a four-step transform with
- * each operand a pair of half-precision numbers (hi + lo; products
+/* DFT inside the analysis (FP32 plans only; at most one; default MP_DFT_F32,
+ * the FFT in FP32).  MP_DFT_F64 runs the window products and the FFT in FP64
+ * and rounds the coefficients to the plan's FP32 (systems need M <= 16384).
+ * The split variants run the DFT on matrix cores as a four-step transform
+ * with each operand a pair of half-precision numbers (hi + lo; products
  * hi*hi + hi*lo + lo*hi accumulated in FP32); systems need M <= 16384. */
+#define MP_DFT_F32 0x0u          /* FFT in FP32 (default)                           */
+#define MP_DFT_F64 0x200u        /* FFT in FP64, coefficients rounded to FP32        */
 #define MP_DFT_F16SPLIT 0x40u    /* FP16 pairs                                      */
 #define MP_DFT_BF16SPLIT 0x80u   /* BF16 pairs                                      */
 /* Pedantic selection (Sec. 5): choose the atom whose real-pair projection
@@ -152,8 +156,8 @@ typedef struct {
  * MP_PREC_F64), MP_SCHED_* (not with MP_PREC_F64).  Uses the
  * current HIP device; blocks until the kernels are built.  *out receives the
  * plan.  MP_E_LIMIT: a frame's FFT exceeds the LDS of one workgroup (M/2
- * complex entries; twice that for MP_DFT_*), or the signal's tree groups do
- * not fit it. */
+ * complex entries of the DFT's precision; twice that for the split
+ * MP_DFT_*), or the signal's tree groups do not fit it. */
 int mp_plan_create(const mp_dict *dicts, int32_t W, const int64_t *L,
                    int32_t batch, double kernel_tol, uint32_t flags,
                    mp_plan **out);

@@ -35,7 +35,7 @@ hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs
                            int MR, const int64_t* frame_prefix, int batch, int64_t frames, const float* win,
                            const void* tw, int N1, int N2, const uint16_t* F1, const uint16_t* F2, void* planes,
                            void* leaves, const void* gam, int pedantic, hipStream_t st);
-hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
+hipError_t launch_dgt(bool f64, bool dft64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
                       const void* win, const void* tw, void* planes, void* leaves, const void* gam, int pedantic,
                       hipStream_t st);
@@ -293,11 +293,12 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
   *out = nullptr;
   if (!dicts || !L || W < 1 || W > MAXW || batch < 1 || batch > (1 << 20)) return MP_E_ARG;
   if (!(kernel_tol >= 0.0 && kernel_tol < 1.0)) return MP_E_ARG;
-  if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA | MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT | MP_PEDANTIC |
-                MP_SCHED_NT512 | MP_SCHED_G128))
+  if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA | MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT | MP_DFT_F64 |
+                MP_PEDANTIC | MP_SCHED_NT512 | MP_SCHED_G128))
     return MP_E_ARG;
   const uint32_t dftf = flags & (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT);
-  if (dftf == (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT) || (dftf && (flags & MP_PREC_F64))) return MP_E_ARG;
+  const uint32_t dfts = flags & (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT | MP_DFT_F64);
+  if ((dfts & (dfts - 1)) || (dfts && (flags & MP_PREC_F64))) return MP_E_ARG;  // at most one, FP32 plans only
   if ((flags & MP_PREC_F64) && (flags & (MP_SCHED_NT512 | MP_SCHED_G128))) return MP_E_ARG;
   int rc = check_dicts(dicts, W);
   if (rc) return rc;
@@ -305,7 +306,8 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     if (L[s] <= 0) return MP_E_ARG;
   // the DGT keeps one frame's half-length FFT in LDS
   for (int w = 0; w < W; ++w)
-    if ((size_t)(dicts[w].M / 2 + (dftf ? dicts[w].M / 2 : dicts[w].M / 64)) * ((flags & MP_PREC_F64) ? 16 : 8) >
+    if ((size_t)(dicts[w].M / 2 + (dftf ? dicts[w].M / 2 : dicts[w].M / 64)) *
+            ((flags & (MP_PREC_F64 | MP_DFT_F64)) ? 16 : 8) >
         160 * 1024)
       return MP_E_LIMIT;
   {
@@ -848,19 +850,22 @@ int mp_autotune(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t batch
 int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream) {
   if (!p || !x_dev || (dtype != MP_DTYPE_F32 && dtype != MP_DTYPE_F64)) return MP_E_ARG;
   int rc = MP_OK;
-  const void* win = p->f64 ? (const void*)p->d_win64 : (const void*)p->d_win32;
+  const bool dft64 = !p->f64 && (p->flags & MP_DFT_F64);  // FP64 DFT for an FP32 plan
+  const bool r64 = p->f64 || dft64;
+  const void* win = r64 ? (const void*)p->d_win64 : (const void*)p->d_win32;
   HCHK(hipEventRecord(p->ev[0], stream));
   HCHK(launch_energy(x_dev, dtype, p->d_sigs, p->batch, p->d_epart, p->d_state, stream));
   for (int w = 0; w < p->W; ++w) {
     const DictDev& D = p->hd[w];
-    const void* tw = p->f64 ? (const void*)(p->d_tw64 + D.tw_off) : (const void*)(p->d_tw32 + D.tw_off);
+    const void* tw = p->dft_fmt >= 0 ? (const void*)(p->d_tw32 + D.tw_off)
+                     : (r64 ? (const void*)(p->d_tw64 + D.tw_off) : (const void*)(p->d_tw32 + D.tw_off));
     if (p->dft_fmt >= 0)
       HCHK(launch_dgt_mfma(p->dft_fmt, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w],
                            p->batch, p->frames_total[w], p->d_win32 + D.win_off, tw, p->dft_n1[w],
                            p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
     else
-      HCHK(launch_dgt(p->f64, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w], p->batch,
-                      p->frames_total[w], (const char*)win + D.win_off * (p->f64 ? 8 : 4), tw, p->d_planes,
+      HCHK(launch_dgt(p->f64, dft64, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w], p->batch,
+                      p->frames_total[w], (const char*)win + D.win_off * (r64 ? 8 : 4), tw, p->d_planes,
                       p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
   }
   HCHK(hipEventRecord(p->ev[1], stream));
@@ -969,7 +974,9 @@ int mp_run_resets(mp_plan* p, const void* x_dev, int32_t dtype, int64_t max_atom
     a.reset_db = reset_db;
     HCHK(hipEventRecord(p->ev[3], stream));
     HCHK(launch_reset_init(x_dev, dtype, p->d_sigs, p->batch, p->max_Lp, p->d_roff, p->d_res, stream));
-    const void* win = p->f64 ? (const void*)p->d_win64 : (const void*)p->d_win32;
+    const bool dft64 = !p->f64 && (p->flags & MP_DFT_F64);
+    const bool r64 = p->f64 || dft64;
+    const void* win = r64 ? (const void*)p->d_win64 : (const void*)p->d_win32;
     for (;;) {
       // inner loop: approximate MP on the current residual's coefficients
       HCHK(launch_mp(p->f64, p->nt, a, p->grid, stream));
@@ -983,15 +990,17 @@ int mp_run_resets(mp_plan* p, const void* x_dev, int32_t dtype, int64_t max_atom
       // finished, so that their planes hold the analysis of the final residual)
       for (int w = 0; w < p->W; ++w) {
         const DictDev& D = p->hd[w];
-        const void* tw = p->f64 ? (const void*)(p->d_tw64 + D.tw_off) : (const void*)(p->d_tw32 + D.tw_off);
+        const void* tw = p->dft_fmt >= 0 ? (const void*)(p->d_tw32 + D.tw_off)
+                         : (r64 ? (const void*)(p->d_tw64 + D.tw_off) : (const void*)(p->d_tw32 + D.tw_off));
         if (p->dft_fmt >= 0)
           HCHK(launch_dgt_mfma(p->dft_fmt, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR,
                                p->d_fprefix[w], p->batch, p->frames_total[w], p->d_win32 + D.win_off, tw,
                                p->dft_n1[w], p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves,
                                (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
         else
-          HCHK(launch_dgt(p->f64, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w],
-                          p->batch, p->frames_total[w], (const char*)win + D.win_off * (p->f64 ? 8 : 4), tw,
+          HCHK(launch_dgt(p->f64, dft64, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR,
+                          p->d_fprefix[w], p->batch, p->frames_total[w],
+                          (const char*)win + D.win_off * (r64 ? 8 : 4), tw,
                           p->d_planes, p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
       }
       HCHK(hipStreamSynchronize(stream));

@@ -476,13 +476,16 @@ __device__ __forceinline__ int64_t xcd_frame() {
 
 __device__ __forceinline__ int dgt_sw(int i) { return i + (i >> 5); }
 
-template <typename R, typename XT>
+// R: arithmetic of the window products and the FFT; O: the plan's
+// coefficient type (planes, leaves, selection scores), O = R except for an
+// FP32 plan with the FP64 DFT.
+template <typename R, typename XT, typename O>
 __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const SigDev* __restrict__ sigs,
                                              int w, int gl, int a, int M, int logM, int MR,
                                              const int64_t* __restrict__ frame_prefix, int batch,
                                              const R* __restrict__ win, const Cx<R>* __restrict__ tw,
-                                             Cx<R>* __restrict__ planes, Leaf<R>* __restrict__ leaves,
-                                             const Cx<R>* __restrict__ gam, int pedantic) {
+                                             Cx<O>* __restrict__ planes, Leaf<O>* __restrict__ leaves,
+                                             const Cx<O>* __restrict__ gam, int pedantic) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem_raw);
   const int H = M >> 1, logH = logM - 1;
@@ -595,9 +598,9 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
   }
   // unpack, write the plane row and the leaves: leaf i = maximum of |rho|^2
   // over bins 16 i .. 16 i + 15 (ties to the lowest bin), one DPP row per leaf
-  Cx<R>* out = planes + S.coef_base + S.off[w] + n * MR;
+  Cx<O>* out = planes + S.coef_base + S.off[w] + n * MR;
   const int lpf = (MR + ROW - 1) >> LOG_ROW;
-  Leaf<R>* lf = leaves + S.leaf_base + S.lbase[w] + n * lpf;
+  Leaf<O>* lf = leaves + S.leaf_base + S.lbase[w] + n * lpf;
   const uint32_t p0 = (uint32_t)(S.off[w] + n * MR);
   const int lane = threadIdx.x & 63;
   // twiddle of bin m (e^{-2 pi i m / M}; -1 at m = H), fetched one pass ahead
@@ -611,24 +614,24 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
     const bool valid = m < MR;
     const Cx<R> t = tnext;
     if (m0 + (int)blockDim.x < lpf * ROW) tnext = twid(m + (int)blockDim.x);
-    Cx<R> v = {(R)0, (R)0};
+    Cx<O> v = {(O)0, (O)0};
     if (valid) {
       const Cx<R> zk = buf[dgt_sw(m & (H - 1))], zr = buf[dgt_sw((H - m) & (H - 1))];
       // even part (zk + conj zr) / 2, odd part (zk - conj zr) / (2i)
       const R er = (R)0.5 * (zk.re + zr.re), ei = (R)0.5 * (zk.im - zr.im);
       const R or_ = (R)0.5 * (zk.im + zr.im), oi = (R)0.5 * (zr.re - zk.re);
-      v.re = er + (t.re * or_ - t.im * oi);
-      v.im = ei + (t.re * oi + t.im * or_);
+      v.re = (O)(er + (t.re * or_ - t.im * oi));
+      v.im = (O)(ei + (t.re * oi + t.im * or_));
       out[(uint32_t)m] = v;
     }
     const bool ped = pedantic && valid && m != 0 && m != H;
-    const R val = sel_score<R>(v.re, v.im, ped ? gam[m] : Cx<R>{(R)0, (R)0}, ped);
+    const O val = sel_score<O>(v.re, v.im, ped ? gam[m] : Cx<O>{(O)0, (O)0}, ped);
     const uint64_t bits = valid ? val_bits(val) : 0ull;
-    const uint64_t rm = row_max_bits<R>(bits);
+    const uint64_t rm = row_max_bits<O>(bits);
     const uint64_t bal = __ballot(valid && bits == rm);
     const uint32_t rowbits = (uint32_t)(bal >> (lane & ~(ROW - 1))) & 0xFFFFu;
     if (rowbits && lane == (lane & ~(ROW - 1)) + __ffs(rowbits) - 1)
-      lf[(uint32_t)m >> LOG_ROW] = make_leaf(KeyOps<R>::make(val, p0 + (uint32_t)m), v.re, v.im);
+      lf[(uint32_t)m >> LOG_ROW] = make_leaf(KeyOps<O>::make(val, p0 + (uint32_t)m), v.re, v.im);
   }
 }
 
@@ -2423,45 +2426,40 @@ hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch
   return hipGetLastError();
 }
 
-hipError_t launch_dgt(bool f64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
+hipError_t launch_dgt(bool f64, bool dft64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
                       const void* win, const void* tw, void* planes, void* leaves, const void* gam, int pedantic,
                       hipStream_t st) {
   if (frames <= 0) return hipSuccess;
   int logM = 0;
   while ((1 << logM) < M) ++logM;
-  const size_t sh = (size_t)(M / 2 + M / 64) * (f64 ? 16 : 8);  // H entries + one pad per 32
+  const bool r64 = f64 || dft64;  // FFT arithmetic in FP64
+  const size_t sh = (size_t)(M / 2 + M / 64) * (r64 ? 16 : 8);  // H entries + one pad per 32
   if (sh > 160 * 1024) return hipErrorInvalidValue;
   const dim3 grid((unsigned)frames);
   // threads per frame: H / 2 (one radix-2 pair per thread, two samples per
   // thread in the load), clamped to 64 .. 256
   const int nt = M / 4 < 64 ? 64 : (M / 4 > 256 ? 256 : M / 4);
-  const void* kf = f64 ? (dtype == 0 ? (const void*)k_dgt<double, float> : (const void*)k_dgt<double, double>)
-                       : (dtype == 0 ? (const void*)k_dgt<float, float> : (const void*)k_dgt<float, double>);
-  if (sh > 64 * 1024) CHK(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+#define MPG_DGT(RT, XTT, OT)                                                                                \
+  do {                                                                                                      \
+    if (sh > 64 * 1024)                                                                                     \
+      CHK(hipFuncSetAttribute((const void*)k_dgt<RT, XTT, OT>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                              (int)sh));                                                                    \
+    k_dgt<RT, XTT, OT><<<grid, nt, sh, st>>>((const XTT*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,      \
+                                             batch, (const RT*)win, (const Cx<RT>*)tw, (Cx<OT>*)planes,     \
+                                             (Leaf<OT>*)leaves, (const Cx<OT>*)gam, pedantic);              \
+  } while (0)
   if (f64) {
-    if (dtype == 0)
-      k_dgt<double, float><<<grid, nt, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
-                                                  batch, (const double*)win, (const Cx<double>*)tw,
-                                                  (Cx<double>*)planes, (Leaf<double>*)leaves,
-                                                  (const Cx<double>*)gam, pedantic);
-    else
-      k_dgt<double, double><<<grid, nt, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
-                                                   batch, (const double*)win, (const Cx<double>*)tw,
-                                                   (Cx<double>*)planes, (Leaf<double>*)leaves,
-                                                  (const Cx<double>*)gam, pedantic);
+    if (dtype == 0) MPG_DGT(double, float, double);
+    else MPG_DGT(double, double, double);
+  } else if (dft64) {
+    if (dtype == 0) MPG_DGT(double, float, float);
+    else MPG_DGT(double, double, float);
   } else {
-    if (dtype == 0)
-      k_dgt<float, float><<<grid, nt, sh, st>>>((const float*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
-                                                 batch, (const float*)win, (const Cx<float>*)tw,
-                                                 (Cx<float>*)planes, (Leaf<float>*)leaves,
-                                                 (const Cx<float>*)gam, pedantic);
-    else
-      k_dgt<float, double><<<grid, nt, sh, st>>>((const double*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,
-                                                  batch, (const float*)win, (const Cx<float>*)tw,
-                                                  (Cx<float>*)planes, (Leaf<float>*)leaves,
-                                                 (const Cx<float>*)gam, pedantic);
+    if (dtype == 0) MPG_DGT(float, float, float);
+    else MPG_DGT(float, double, float);
   }
+#undef MPG_DGT
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ MP_WIN_BLACKMAN, MP_WIN_HANN, MP_WIN_GAUSS = 0, 1, 2
 MP_PREC_F32, MP_PREC_F64 = 0x0, 0x1
 MP_THR_REL, MP_CONJ_GATE_GAMMA = 0x10, 0x20
 MP_DFT_F16SPLIT, MP_DFT_BF16SPLIT = 0x40, 0x80
+MP_DFT_F32, MP_DFT_F64 = 0x0, 0x200
 MP_PEDANTIC = 0x100
 MP_SCHED_NT512, MP_SCHED_G128 = 0x1000, 0x2000
 MP_DTYPE_F32, MP_DTYPE_F64 = 0, 1
