@@ -102,6 +102,9 @@ int orc_check_dicts(const orc_dict *d, int32_t W) {
     if (d[w].a <= 0 || d[w].M <= 0 || d[w].gl <= 0) return ORC_E_ARG;
     if (!is_pow2(d[w].M) || d[w].M < 2) return ORC_E_GRID;
     if ((d[w].gl & 1) || d[w].gl > 8 * d[w].M) return ORC_E_GRID;
+    /* Blackman or Hann of length 2: a single nonzero sample makes every atom
+       real, and Eq. (dualatprod) for a pair would divide by 1 - |gamma|^2 = 0 */
+    if (d[w].gl == 2 && d[w].window != ORC_WIN_GAUSS && d[w].M >= 4) return ORC_E_ARG;
   }
   return ORC_OK;
 }

@@ -203,6 +203,10 @@ int check_dicts(const mp_dict* d, int W) {
     if (d[w].gl <= 0 || d[w].a <= 0 || d[w].M <= 0) return MP_E_ARG;
     if (!is_pow2(d[w].M) || d[w].M < 2) return MP_E_GRID;
     if ((d[w].gl & 1) || (int64_t)d[w].gl > 8 * (int64_t)d[w].M) return MP_E_GRID;  // longer than M: folded
+    // a periodic Blackman or Hann window of length 2 has one nonzero sample:
+    // every atom is real, so a pair's d and conj d coincide and the pair
+    // adjustment (Eq. dualatprod) divides by 1 - |gamma|^2 = 0
+    if (d[w].gl == 2 && d[w].window != MP_WIN_GAUSS && d[w].M >= 4) return MP_E_ARG;
   }
   // hops need not nest nor divide M: each pair lives on the common grid
   // gcd(a_w, a_v) x lcm(M_w, M_v) (Sec. 4.2), lcm = max for powers of two

@@ -44,6 +44,7 @@ def test_strerror_and_argument_errors_without_gpu():
         ([(0, 64, 16, 64)], [1024], 1.5, 0, mpg.MP_E_ARG),                      # eps >= 1
         ([(5, 64, 16, 64)], [1024], 1e-4, 0, mpg.MP_E_ARG),                     # window
         ([(0, 64, 16, 64)], [1024], 1e-4, 0x400, mpg.MP_E_ARG),                 # flags
+        ([(1, 2, 1, 4)], [64], 1e-4, 0, mpg.MP_E_ARG),                          # one-sample window: real atoms
         ([(0, 64, 16, 64)], [1024], 1e-4, 0x201, mpg.MP_E_ARG),                 # FP64 DFT flag on an FP64 plan
         ([(0, 64, 16, 64)], [1024], 1e-4, 0x240, mpg.MP_E_ARG),                 # two DFT choices
         ([(0, 32768, 8192, 32768)], [65536], 1e-4, 0x200, mpg.MP_E_LIMIT),      # FP64 DFT frame exceeds LDS

@@ -258,6 +258,71 @@ def test_p5_eps0_equals_textbook(dicts, L, seed):
     assert np.max(np.abs(r.E[:k] - E[:k])) < 1e-12 * r.E0
 
 
+from hypothesis import event, given, settings, HealthCheck, strategies as st
+
+
+@st.composite
+def _small_systems(draw):
+    """One or two Gabor systems (any window, M a power of two up to 64, hops
+    that need not divide M or nest, windows up to 2M) and a length that the
+    plan accepts."""
+    W = draw(st.integers(1, 2))
+    dicts = []
+    while len(dicts) < W:
+        M = 2 ** draw(st.integers(2, 6))
+        gl = 2 * draw(st.integers(2, M))  # 4 .. 2M samples (one-sample windows are rejected)
+        a = draw(st.sampled_from(sorted({max(1, M // 8), max(1, M // 4), M // 2, M,
+                                          max(1, 3 * M // 8), max(1, 3 * M // 4)})))
+        d = (draw(st.integers(0, 2)), gl, a, M)
+        if d not in dicts:  # two equal systems would tie exactly
+            dicts.append(d)
+    L = draw(st.integers(16, 200))
+    return dicts, L, draw(st.integers(0, 2 ** 31 - 1))
+
+
+@settings(max_examples=40, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.filter_too_much])
+@given(_small_systems())
+def test_p5_random_small_configs_equal_textbook(cfg):
+    # property-based P5: on random small configurations the oracle at eps = 0
+    # selects what textbook MP selects, up to the first selection whose top-2
+    # gap is too small for the two arithmetics to agree on
+    dicts, L, seed = cfg
+    Lp = O.padded_length(dicts, L)
+    if Lp > 512 or Lp < max(d[1] for d in dicts) * 2:
+        event("skipped: too long or rejected")
+        return  # too long for the explicit dictionary, or rejected by the plan rules
+    x = np.random.default_rng(seed).standard_normal(L)
+    xp = np.zeros(Lp)  # the oracle zero-pads to the plan length; the textbook works on that signal
+    xp[:L] = x
+    n_it = 40
+    r = O.mp(dicts, x, 0.0, K=n_it)
+    w, m, n, c, E = T.mp(dicts, xp, min(n_it, r.n_atoms))
+    small = np.nonzero(r.gap[:r.n_atoms] < 1e-9)[0]
+    k = min(r.n_atoms, len(w), int(small[0]) if len(small) else r.n_atoms)  # before the first near-tie
+    event("compared %s selections" % ("all" if k == r.n_atoms else "some"))
+    assert np.array_equal(r.w[:k], w[:k]) and np.array_equal(r.m[:k], m[:k]) and np.array_equal(r.n[:k], n[:k])
+    if k:
+        assert np.max(np.abs(r.c[:k] - c[:k]) / np.abs(c[:k])) < 1e-10
+        assert np.max(np.abs(r.E[:k] - E[:k])) < 1e-11 * r.E0
+
+
+def test_one_sample_windows_rejected():
+    # a periodic Blackman or Hann window of length 2 is nonzero at one sample
+    # only: every atom is real, so a pair's d and conj d coincide and
+    # Eq. (dualatprod) would divide by 1 - |gamma|^2 = 0 (or by its rounding
+    # residue); the Gaussian of
+    # length 2 and frames of M = 2 (DC and Nyquist only) have no such pairs
+    for win in (O.WIN_BLACKMAN, O.WIN_HANN):
+        assert O.padded_length([(win, 2, 1, 4)], 64) < 0
+        assert O.padded_length([(win, 2, 1, 2)], 64) == 64
+        g = T._window(win, 2, 1, 4)
+        assert np.count_nonzero(np.abs(g) > 1e-12) == 1  # Blackman's other sample rounds to ~1e-17
+        d = T.atom((win, 2, 1, 4), 1, 3, 16)
+        assert np.max(np.abs(d.imag)) < 1e-12  # the m = 1 atom is real up to that rounding
+    assert O.padded_length([(O.WIN_GAUSS, 2, 1, 4)], 64) == 64
+
+
 @pytest.mark.parametrize("dicts,L,seed", [
     ([(0, 32, 8, 32), (0, 64, 16, 64)], 256, 31),
     ([(1, 16, 4, 16), (0, 32, 8, 32)], 128, 32),
