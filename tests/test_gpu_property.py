@@ -1,0 +1,77 @@
+"""Property-based parity of the HIP path with the oracle on random small
+configurations: one to three Gabor systems with any window, frame lengths
+8 .. 256, windows up to twice the frame, hops that divide M or not, ragged
+signal lengths.  FP64 plans must select what the oracle selects (up to the
+first selection whose oracle top-2 gap is below 1e-10, where rounding may
+legitimately decide); FP32 plans follow the FP32 rule of the other tests."""
+import numpy as np
+import pytest
+from hypothesis import given, settings, HealthCheck, strategies as st
+
+from oracle import core as O
+from gpu_helpers import gpu_run, oracle_run, first_mismatch, assert_tolerance
+
+pytestmark = pytest.mark.gpu
+F64 = 0x1
+
+
+@st.composite
+def _systems(draw):
+    W = draw(st.integers(1, 3))
+    dicts = []
+    while len(dicts) < W:
+        M = 2 ** draw(st.integers(3, 8))
+        gl = 2 * draw(st.integers(2, M))
+        a = draw(st.sampled_from(sorted({M // 8, M // 4, M // 2, M, 3 * M // 8, 3 * M // 4})))
+        d = (draw(st.integers(0, 2)), gl, a, M)
+        if d not in dicts:
+            dicts.append(d)
+    L = draw(st.integers(64, 4096))
+    return dicts, L, draw(st.integers(0, 2 ** 31 - 1))
+
+
+def _signal(L, seed):
+    return np.random.default_rng(seed).standard_normal(L)
+
+
+_SETTINGS = settings(max_examples=20, deadline=None, derandomize=True,
+                     suppress_health_check=[HealthCheck.too_slow, HealthCheck.filter_too_much])
+
+
+@_SETTINGS
+@given(_systems())
+def test_random_configs_fp64_same_selections(cfg):
+    pytest.importorskip("torch")
+    dicts, L, seed = cfg
+    Lp = O.padded_length(dicts, L)
+    if Lp < 0 or Lp > 16384:
+        return
+    x = _signal(L, seed)
+    K = 150
+    print("fp64 case", dicts, L, seed, flush=True)
+    _, ga = gpu_run(dicts, [x], 1e-4, K=K, flags=F64)
+    orc = oracle_run(dicts, x, 1e-4, K=K)
+    small = np.nonzero(orc.gap < 1e-10)[0]
+    upto = int(small[0]) if len(small) else orc.n_atoms
+    fm = first_mismatch(ga[0], orc)
+    assert fm >= upto, "differs at %d before the first near-tie at %d: %s" % (fm, upto, dicts)
+    if upto:
+        c = ga[0]["re"][:upto] + 1j * ga[0]["im"][:upto]
+        assert np.max(np.abs(c - orc.c[:upto])) <= 1e-9 * np.max(np.abs(orc.c))
+        assert np.max(np.abs(ga[0]["E_after"][:upto] - orc.E[:upto])) <= 1e-12 * orc.E0
+
+
+@_SETTINGS
+@given(_systems())
+def test_random_configs_fp32_rule(cfg):
+    pytest.importorskip("torch")
+    dicts, L, seed = cfg
+    Lp = O.padded_length(dicts, L)
+    if Lp < 0 or Lp > 16384:
+        return
+    x = _signal(L, seed).astype(np.float32)
+    K = 150
+    print("fp32 case", dicts, L, seed, flush=True)
+    _, ga = gpu_run(dicts, [x], 1e-4, K=K, flags=0)
+    orc = oracle_run(dicts, x, 1e-4, K=K, x_dtype=np.float32)
+    assert_tolerance(ga[0], orc)
