@@ -311,6 +311,35 @@ def test_mp_fp32_schedules_identical_and_autotune():
         assert np.array_equal(plan.atoms(s), ref[s])
 
 
+def test_mp_fp32_loop_with_fp64_dft():
+    # FP32 plan whose analysis DFT runs in FP64 (MP_DFT_F64): the loop follows
+    # the FP32 rule, and the initial coefficients are the FP64 ones rounded
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024)]
+    lens = [16384, 9000]
+    xs = [S.audio_like(L, S.rng(82, i)).astype(np.float32) for i, L in enumerate(lens)]
+    _, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=mpg.MP_DFT_F64)
+    for i, x in enumerate(xs):
+        orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32)
+        assert_tolerance(ga[i], orc)
+
+
+def test_autotune_fp64_plan_has_one_schedule():
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 64, 16, 64), (0, 128, 32, 128)]
+    x = np.random.default_rng(83).standard_normal(2048)
+    xt = torch.from_numpy(x).cuda()
+    plan, rep = mpg.Plan.autotuned(dicts, [len(x)], xt, 1e-4, F64, probe_atoms=50)
+    assert len(rep["schedules"]) == 1 and rep["chosen"] == 0
+    assert plan.stats().threads == rep["schedules"][0]["threads"]
+    plan.analyze(xt)
+    plan.run(300)
+    torch.cuda.synchronize()
+    assert_identical(plan.atoms(0), oracle_run(dicts, x, 1e-4, K=300))
+
+
 def test_mp_fp32_batch_ragged():
     _torch()
     dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)]
