@@ -296,6 +296,7 @@ def main():
         "mp_loop_atoms_per_s": loop_rate,
         "analyze_ms": analyze_ms,
         "dgt": {"ms": st.dgt_ms, "GB_per_s": dgt_gbps, "bytes": dgt_bytes,
+                "frac_of_peak": (dgt_gbps / HBM_PEAK_GBPS) if dgt_gbps else None,
                 "frac_of_copy": (dgt_gbps / copy_gbps) if dgt_gbps else None},
         "copy_GB_per_s": copy_gbps,
         "fp64_plain": fp64,
