@@ -465,13 +465,15 @@ def test_resets_fp64_identical(eps, reset_it):
         assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
 
 
-def test_resets_fp32_batch_reach_true_target():
+@pytest.mark.parametrize("dft", ["f32", "f64"])
+def test_resets_fp32_batch_reach_true_target(dft):
+    # dft f64: the re-analyses of the true residual run the FP64 DFT too
     torch = _torch()
     from paper_2202_12380_amd import mpg
     dicts = [(0, 64, 16, 64), (0, 256, 64, 256)]
     lens = [2048, 3000, 4096]
     xs = [np.random.default_rng(20 + i).standard_normal(L).astype(np.float32) for i, L in enumerate(lens)]
-    plan = mpg.Plan(dicts, lens, 5e-2, 0)
+    plan = mpg.Plan(dicts, lens, 5e-2, mpg.MP_DFT_F64 if dft == "f64" else 0)
     plan.analyze(torch.from_numpy(np.concatenate(xs)).cuda())
     plan.run_resets(100000, 30.0, 200, -6.0)
     for s, x in enumerate(xs):
