@@ -1803,9 +1803,10 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     {
       int ws = 0;
       for (int w = 1; w < W; ++w) ws += (int)rdlane32((uint32_t)sb, w) <= lane ? 1 : 0;
-      const int4 ga = *reinterpret_cast<const int4*>(&tgb[ws].gA_lo);
-      const int c = lane - tgb[ws].slot_base;
-      const int g = c < ga.y ? ga.x + c : ga.z + (c - ga.y);
+      // target ws's runs from its lane's registers (cross-lane moves, no LDS read-back)
+      const int gal = __shfl(T.gA_lo, ws), gan = __shfl(T.gA_n, ws), gbl = __shfl(T.gB_lo, ws);
+      const int c = lane - __shfl(sb, ws);
+      const int g = c < gan ? gal + c : gbl + (c - gan);
       itb->glist[lane] = lane < TG ? g : 0;
     }
     // coefficient adjustment for the pair, Eq. (dualatprod), and energy
