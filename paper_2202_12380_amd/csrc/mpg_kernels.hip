@@ -1849,6 +1849,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     Cx<float> cc;
     double Et;
     int ibase, sbase, g0, g1;
+    int gl;  // touched-group list entry `lane` (used by wave 0)
   };
   auto read_it = [&](int b) -> ItR {
     const It32* itb = it2 + b;
@@ -1862,6 +1863,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     r.sbase = lane < W ? itb->sbase[lane] : 0x7fffffff;
     r.g0 = itb->glist[wave];
     r.g1 = itb->glist[wave + NW];
+    r.gl = wave == 0 ? itb->glist[lane] : 0;
     return r;
   };
 
@@ -2076,7 +2078,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     // next selection unless a touched group ends above it.
     if (wave == 0) {
       if (TG <= 64) {
-        if (lane < TG) gkey[it2[cur].glist[lane]] = 0ull;
+        if (lane < TG) gkey[cr.gl] = 0ull;
       } else {
         for (int w = 0; w < W; ++w) {
           const int4 a = *reinterpret_cast<const int4*>(&tg[w].gA_lo);
