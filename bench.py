@@ -114,7 +114,7 @@ def main():
         noise_study(args)
         return
     if args.gpus != 1:
-        sys.stderr.write("bench.py measures one GPU only: this build runs on a single MI355X and has "
+        sys.stderr.write("bench.py measures one GPU only: the library runs on a single MI355X and has "
                          "no multi-GPU path (signals would shard across GPUs with no exchange). "
                          "Run with --gpus 1.\n")
         sys.exit(2)
