@@ -17,6 +17,7 @@ WIN_GAUSS = 2      # exp(-pi t^2 / (a M)): its width depends on the lattice
 THR_REL = 1
 CONJ_GATE_GAMMA = 2
 PEDANTIC = 4
+KEEP_BOX = 8       # keep the survivors' whole bounding box (a reading, see the header)
 
 STOP_K, STOP_SNR, STOP_ENEG, STOP_ZERO = 1, 2, 3, 4
 
@@ -59,6 +60,9 @@ def lib():
         _lib.orc_mp.argtypes = [C.POINTER(_Dict), C.c_int32, dp, C.c_int64, C.c_double,
                                 C.c_uint32, C.c_int64, C.c_double, C.c_int64, ip, ip, ip,
                                 dp, dp, dp, dp, C.c_void_p, C.c_void_p, C.POINTER(_Stats)]
+        _lib.orc_mp_replay.argtypes = [C.POINTER(_Dict), C.c_int32, dp, C.c_int64, C.c_double,
+                                       C.c_uint32, C.c_int64, ip, ip, ip, dp, dp, dp, dp, dp, dp,
+                                       C.c_void_p, C.c_void_p, C.POINTER(_Stats)]
         _lib.orc_resynth.argtypes = [C.POINTER(_Dict), C.c_int32, C.c_int64, C.c_int64,
                                      ip, ip, ip, dp, dp, dp]
     return _lib
@@ -201,6 +205,55 @@ def mp(dicts, x: np.ndarray, eps: float, K: int = 0, target_db: float = 0.0,
                     planes)
 
 
+@dataclass
+class ReplayResult:
+    c: np.ndarray       # adjusted coefficient of each replayed atom (oracle arithmetic)
+    E: np.ndarray       # error estimate after each step
+    gap: np.ndarray     # top-2 gap of the oracle's scores before each step
+    best: np.ndarray    # largest selection score before each step
+    chosen: np.ndarray  # score of the replayed atom before each step
+    E0: float
+    L_padded: int
+    planes: list        # residual planes after the last step (or None)
+
+
+def mp_replay(dicts, x: np.ndarray, eps: float, w, m, n, flags: int = 0,
+              return_planes: bool = False) -> ReplayResult:
+    """Runs the oracle's loop on x with the selections (w, m, n) of another run
+    instead of its own maxima (orc_mp_replay)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    L = len(x)
+    Lp = padded_length(dicts, L)
+    if Lp < 0:
+        raise RuntimeError("oracle error %d" % Lp)
+    w = np.ascontiguousarray(w, np.int32)
+    m = np.ascontiguousarray(m, np.int32)
+    n = np.ascontiguousarray(n, np.int32)
+    k = len(w)
+    sz = max(k, 1)
+    cre, cim, Ea, gp, best, ch = (np.zeros(sz) for _ in range(6))
+    if k == 0:
+        w = m = n = np.zeros(1, np.int32)
+    sizes = [(Lp // d[2]) * (d[3] // 2 + 1) for d in dicts]
+    fr = fi = None
+    if return_planes:
+        fr = np.zeros(sum(sizes))
+        fi = np.zeros(sum(sizes))
+    st = _Stats()
+    _check(lib().orc_mp_replay(_dicts(dicts), len(dicts), x, L, eps, flags, k, w, m, n,
+                               cre, cim, Ea, gp, best, ch,
+                               fr.ctypes.data if fr is not None else None,
+                               fi.ctypes.data if fi is not None else None, C.byref(st)))
+    planes = None
+    if return_planes:
+        planes, o = [], 0
+        for d, s in zip(dicts, sizes):
+            planes.append((fr[o:o + s] + 1j * fi[o:o + s]).reshape(Lp // d[2], d[3] // 2 + 1))
+            o += s
+    return ReplayResult(cre[:k] + 1j * cim[:k], Ea[:k].copy(), gp[:k].copy(), best[:k].copy(),
+                        ch[:k].copy(), st.E0, st.L_padded, planes)
+
+
 def resynth(dicts, Lp: int, w, m, n, c) -> np.ndarray:
     w = np.ascontiguousarray(w, np.int32)
     m = np.ascontiguousarray(m, np.int32)
@@ -233,7 +286,7 @@ class ResetResult:
 
 
 def mp_resets(dicts, x: np.ndarray, eps: float, K: int = 0, target_db: float = 0.0,
-              reset_it: int = 1, reset_db: float = 0.0, flags: int = 0) -> ResetResult:
+              reset_it: int = 0, reset_db: float = 0.0, flags: int = 0) -> ResetResult:
     """Approximate coefficient-domain MP with resets (Alg. 2), composed of this
     oracle's own steps.  Each inner loop is mp() (Alg. 1) started from the
     coefficients of the current true residual, rho = D* r, with error E = ||r||^2;
@@ -243,7 +296,16 @@ def mp_resets(dicts, x: np.ndarray, eps: float, K: int = 0, target_db: float = 0
     subtracts their synthesis (resynth()) from r; ||r||^2 becomes the error.
     The procedure ends when the true error reaches target_db below ||x||^2,
     after K selections (0: L_padded/5), when the coefficients vanish, or when
-    an inner loop selects nothing."""
+    an inner loop selects nothing.  reset_it <= 0 selects the default
+    criterion derived from eps (see below)."""
+    if reset_it <= 0:
+        # the default criterion derived from the kernel threshold (Sec. 7,
+        # 'reset'; a reading, the paper does not print it): ceil(32 / eps)
+        # selections per round, and a reset once the estimate has fallen by
+        # the factor eps below the error at the last reset
+        reset_it = int(math.ceil(32.0 / eps)) if eps > 0 else (1 << 62)
+        if reset_db == 0.0 and eps > 0:
+            reset_db = 10.0 * math.log10(eps)
     x = np.ascontiguousarray(x, dtype=np.float64)
     L = len(x)
     Lp = padded_length(dicts, L)

@@ -315,6 +315,22 @@ int orc_kernel_table(const orc_dict *dw, const orc_dict *dv, double eps,
         im[i] = 0.0;
       }
     }
+  if (flags & ORC_KEEP_BOX) {
+    /* reading of the kernel figure's "fixed size and shape": keep every entry
+     * of the survivors' bounding box, sub-threshold ones included */
+    for (int64_t c = 0; c < ncol; ++c) {
+      if (llabs(c - D) > bd) continue;
+      int64_t Delta = (c - D) * amin;
+      double *cr = re + c * Mmax, *ci = im + c * Mmax;
+      memset(cr, 0, sizeof(double) * Mmax);
+      memset(ci, 0, sizeof(double) * Mmax);
+      for (int64_t s = -dw->gl / 2; s < dw->gl / 2; ++s)
+        cr[mod64(s, Mmax)] += win_at(gv, dv->gl, s + Delta) * win_at(gw, dw->gl, s);
+      orc_fft(Mmax, cr, ci, -1);
+      for (int64_t mu = 0; mu < Mmax; ++mu)
+        if (llabs(cmod64(mu, Mmax)) > bm) cr[mu] = ci[mu] = 0.0;
+    }
+  }
   if (box_mu) *box_mu = bm;
   if (box_delta) *box_delta = bd;
   free(gw), free(gv);
@@ -379,11 +395,17 @@ static void frame_top2(plane *P, int64_t n) {
   P->farg[n] = arg;
 }
 
-int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
-           double eps, uint32_t flags, int64_t K, double target_db,
-           int64_t cap, int32_t *aw, int32_t *am, int32_t *an, double *cre,
-           double *cim, double *E_after, double *gap, double *final_re,
-           double *final_im, orc_stats *st) {
+/* The loop of orc_mp.  With n_forced >= 0 the selections are not taken
+ * from the maximum but from fw / fm / fn (replay of another run): K =
+ * n_forced, no other stop rule, and best / chosen receive the largest score
+ * and the score of the replayed atom at each step. */
+static int mp_core(const orc_dict *d, int32_t W, const double *x, int64_t L,
+                   double eps, uint32_t flags, int64_t K, double target_db,
+                   int64_t cap, int32_t *aw, int32_t *am, int32_t *an,
+                   double *cre, double *cim, double *E_after, double *gap,
+                   double *final_re, double *final_im, orc_stats *st,
+                   int64_t n_forced, const int32_t *fw, const int32_t *fm,
+                   const int32_t *fn, double *best_out, double *chosen_out) {
   int rc = ORC_OK;
   if (!st || !x || eps < 0.0) return ORC_E_ARG;
   memset(st, 0, sizeof(*st));
@@ -391,6 +413,10 @@ int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
   if (Lp < 0) return (int)Lp;
   st->L_padded = Lp;
   if (K <= 0) K = Lp / 5;
+  if (n_forced >= 0) {
+    K = n_forced;
+    target_db = 0.0;
+  }
   if (K > cap) K = cap;
 
   double *xp = calloc((size_t)Lp, sizeof(double));
@@ -479,7 +505,7 @@ int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
       reason = ORC_STOP_SNR;
       break;
     }
-    if (E < 0.0) {
+    if (E < 0.0 && n_forced < 0) {
       reason = ORC_STOP_ENEG;
       break;
     }
@@ -503,7 +529,18 @@ int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
           second = fb;
         }
       }
-    if (!(best > 0.0)) {
+    if (n_forced >= 0) {
+      /* replay: the k-th selection of the other run */
+      v = fw[k];
+      if (v < 0 || v >= W || fm[k] < 0 || fm[k] >= P[v].MR || fn[k] < 0 || fn[k] >= P[v].N) {
+        rc = ORC_E_ARG;
+        goto done;
+      }
+      kk = fm[k];
+      j = fn[k];
+      best_out[k] = best;
+      chosen_out[k] = score(&P[v], kk, P[v].re[j * P[v].MR + kk], P[v].im[j * P[v].MR + kk]);
+    } else if (!(best > 0.0)) {
       reason = ORC_STOP_ZERO;
       break;
     }
@@ -541,7 +578,7 @@ int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
     cre[k] = cr;
     cim[k] = ci;
     E_after[k] = E;
-    gap[k] = (best - (second > 0.0 ? second : 0.0)) / best;
+    gap[k] = best > 0.0 ? (best - (second > 0.0 ? second : 0.0)) / best : 0.0;
     ++k;
 
     /* residual update (Alg. 3): for every target system w and every target
@@ -601,6 +638,36 @@ done:
   if (T)
     for (int32_t i = 0; i < W * W; ++i) free(T[i].re), free(T[i].im);
   free(P), free(T), free(xp);
+  return rc;
+}
+
+int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
+           double eps, uint32_t flags, int64_t K, double target_db,
+           int64_t cap, int32_t *aw, int32_t *am, int32_t *an, double *cre,
+           double *cim, double *E_after, double *gap, double *final_re,
+           double *final_im, orc_stats *st) {
+  return mp_core(d, W, x, L, eps, flags, K, target_db, cap, aw, am, an, cre, cim,
+                 E_after, gap, final_re, final_im, st, -1, NULL, NULL, NULL, NULL,
+                 NULL);
+}
+
+int orc_mp_replay(const orc_dict *d, int32_t W, const double *x, int64_t L,
+                  double eps, uint32_t flags, int64_t n, const int32_t *fw,
+                  const int32_t *fm, const int32_t *fn, double *cre,
+                  double *cim, double *E_after, double *gap, double *best,
+                  double *chosen, double *final_re, double *final_im,
+                  orc_stats *st) {
+  if (n < 0 || (n > 0 && (!fw || !fm || !fn || !cre || !cim || !E_after || !gap ||
+                          !best || !chosen)))
+    return ORC_E_ARG;
+  int32_t *aw = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t *am = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t *an = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int rc = ORC_E_NOMEM;
+  if (aw && am && an)
+    rc = mp_core(d, W, x, L, eps, flags, n, 0.0, n > 0 ? n : 1, aw, am, an, cre, cim,
+                 E_after, gap, final_re, final_im, st, n, fw, fm, fn, best, chosen);
+  free(aw), free(am), free(an);
   return rc;
 }
 

@@ -28,6 +28,7 @@ extern "C" {
 #define ORC_THR_REL 1u         /* threshold relative to each kernel's peak   */
 #define ORC_CONJ_GATE_GAMMA 2u /* conjugate-partner update only if gamma!=0  */
 #define ORC_PEDANTIC 4u        /* select by the pair projection energy       */
+#define ORC_KEEP_BOX 8u        /* keep the survivors' whole bounding box     */
 
 /* return codes */
 #define ORC_OK 0
@@ -60,7 +61,7 @@ int orc_window(int32_t type, int32_t gl, double *g);
 /* as orc_window; the Gaussian's width depends on the lattice (a, M) */
 int orc_window_ga(int32_t type, int32_t gl, int32_t a, int32_t M, double *g);
 
-/* Grid validation (nested a, nested M, M/a integer) and padded length. */
+/* Grid validation (M a power of two, gl even and gl <= 8 M) and padded length. */
 int orc_check_dicts(const orc_dict *d, int32_t W);
 int64_t orc_padded_length(const orc_dict *d, int32_t W, int64_t L);
 
@@ -104,6 +105,20 @@ int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
            int64_t cap, int32_t *aw, int32_t *am, int32_t *an, double *cre,
            double *cim, double *E_after, double *gap, double *final_re,
            double *final_im, orc_stats *st);
+
+/* Replay: the loop of orc_mp with the selections taken from fw / fm / fn
+ * (n of them, e.g. another implementation's run) instead of the maximum.
+ * Every other step is orc_mp's, in its order, on the oracle's own
+ * coefficients.  Per step: adjusted coefficient c~ of the replayed atom,
+ * error estimate after it, top-2 gap, best = largest selection score and
+ * chosen = score of the replayed atom before the step.  No stop rule other
+ * than n.  ORC_E_ARG if a replayed atom lies outside its system's grid. */
+int orc_mp_replay(const orc_dict *d, int32_t W, const double *x, int64_t L,
+                  double eps, uint32_t flags, int64_t n, const int32_t *fw,
+                  const int32_t *fm, const int32_t *fn, double *cre,
+                  double *cim, double *E_after, double *gap, double *best,
+                  double *chosen, double *final_re, double *final_im,
+                  orc_stats *st);
 
 /* Signal-domain synthesis of a list of real atoms into y (length Lp). */
 int orc_resynth(const orc_dict *d, int32_t W, int64_t Lp, int64_t n_atoms,

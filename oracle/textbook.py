@@ -97,3 +97,79 @@ def mp(dicts, x: np.ndarray, n_iter: int, stop_rel: float = 0.0, pedantic: bool 
         if Es[-1] <= stop_rel * E0:
             break
     return (np.array(ws), np.array(ms), np.array(ns), np.array(cs), np.array(Es))
+
+
+def project_sequence(dicts, x: np.ndarray, seq):
+    """Signal-domain MP along a given selection list seq = [(w, m, n), ...]
+    (no selection rule): each step subtracts the least-squares projection of
+    the real residual onto the atom's real pair (span{d} at DC and Nyquist).
+    Returns (c, E, rho) with E[k] = ||r_{k+1}||^2 and rho = D* r after the
+    last step, in global index order."""
+    x = np.asarray(x, np.float64)
+    L = len(x)
+    D, index = dictionary(dicts, L)
+    pos = {t: i for i, t in enumerate(index)}
+    r = x.copy()
+    cs, Es = [], []
+    for (w, m, n) in seq:
+        d = D[:, pos[(w, m, n)]]
+        M = dicts[w][3]
+        if m == 0 or 2 * m == M:
+            c = np.vdot(d, r)       # <r, d>
+            r = r - (c * d).real
+        else:
+            A = np.stack([d, d.conj()], axis=1)
+            sol, *_ = np.linalg.lstsq(A, r.astype(np.complex128), rcond=None)
+            c = sol[0]
+            r = r - (A @ sol).real
+        cs.append(c)
+        Es.append(float(r @ r))
+    return np.array(cs), np.array(Es), D.conj().T @ r
+
+
+def truncated_gram_mp(dicts, x: np.ndarray, eps: float, n_iter: int, gate_gamma: bool):
+    """Approximate coefficient-domain MP written with the Gram matrix of the
+    explicitly built reduced dictionary instead of kernels (Eq. approxResDef
+    with the truncated Gram matrix of Eq. truncgram, the real-atom pairs of
+    Sec. 5 and the pair update of Alg. 3).  G[p, q] = <d_q, d_p> and, for the
+    conjugate partner, Gc[p, q] = <conj d_q, d_p>; both are truncated entry by
+    entry (|.| > eps).  gamma(q) = <d_q, conj d_q>, truncated the same way.
+    gate_gamma: the partner term is applied only when gamma != 0 (the literal
+    condition of Alg. 3); otherwise wherever Gc is nonzero.
+    Returns (w, m, n, c, E, rho_final)."""
+    x = np.asarray(x, np.float64)
+    L = len(x)
+    D, index = dictionary(dicts, L)
+    G = D.conj().T @ D                      # G[p, q] = sum_l d_q(l) conj(d_p(l))
+    Gc = D.conj().T @ D.conj()              # Gc[p, q] = sum_l conj(d_q(l)) conj(d_p(l))
+    G = np.where(np.abs(G) > eps, G, 0)
+    Gc = np.where(np.abs(Gc) > eps, Gc, 0)
+    gam = np.sum(D * D, axis=0)             # <d_q, conj d_q>
+    gam = np.where(np.abs(gam) > eps, gam, 0)
+    rho = D.conj().T @ x
+    E = float(x @ x)
+    ws, ms, ns, cs, Es = [], [], [], [], []
+    for _ in range(n_iter):
+        s = rho.real ** 2 + rho.imag ** 2
+        p = int(np.argmax(s))
+        w, m, n = index[p]
+        M = dicts[w][3]
+        pair = not (m == 0 or 2 * m == M)
+        if pair:
+            g = gam[p]
+            c = (rho[p] - np.conj(g) * np.conj(rho[p])) / (1.0 - abs(g) ** 2)
+            Et = 2.0 * (abs(c) ** 2 + (g * c * c).real)
+        else:
+            c = rho[p]
+            Et = abs(c) ** 2
+        E -= Et
+        upd = c * G[:, p]
+        if pair and (not gate_gamma or gam[p] != 0):
+            upd = upd + np.conj(c) * Gc[:, p]
+        rho = rho - upd
+        ws.append(w)
+        ms.append(m)
+        ns.append(n)
+        cs.append(c)
+        Es.append(E)
+    return np.array(ws), np.array(ms), np.array(ns), np.array(cs), np.array(Es), rho
