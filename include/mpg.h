@@ -45,8 +45,9 @@ extern "C" {
 /* ---- return codes ---- */
 #define MP_OK 0
 #define MP_E_ARG (-1)   /* invalid argument (null pointer, bad size, bad index) */
-#define MP_E_GRID (-2)  /* systems not compatible: a or M not nested, M/a not integer,
-                           M not a power of two, gl odd or gl > 8 M (Sec. 2.1)    */
+#define MP_E_GRID (-2)  /* unsupported Gabor system: M not a power of two, gl odd or
+                           gl > 8 M.  Hops need not nest nor divide M: every pair
+                           lives on its common grid (Sec. 2.1, Sec. 4.2)          */
 #define MP_E_LEN (-3)   /* a padded length is shorter than gl_v + gl_w of some pair  */
 #define MP_E_NOMEM (-4) /* device or host allocation failed                         */
 #define MP_E_HIP (-5)   /* a HIP runtime call failed                                */
@@ -151,7 +152,8 @@ typedef struct {
  * length to a multiple of lcm(a_w, M_w), and precomputes on the device, in
  * FP64, every truncated cross-kernel h_{w,v} on its common grid (Sec. 4.1,
  * 4.2; threshold Eq. truncgram, absolute unless MP_THR_REL) plus FP32 copies.
- * kernel_tol is the threshold epsilon (> 0).  flags: MP_PREC_*, MP_THR_REL,
+ * kernel_tol is the threshold epsilon, 0 <= epsilon < 1 (0 keeps every
+ * entry whose overlap is nonzero; MP_E_ARG otherwise).  flags: MP_PREC_*, MP_THR_REL,
  * MP_CONJ_GATE_GAMMA, MP_PEDANTIC, at most one MP_DFT_* (not with
  * MP_PREC_F64), MP_SCHED_* (not with MP_PREC_F64).  Uses the
  * current HIP device; blocks until the kernels are built.  *out receives the
@@ -220,20 +222,31 @@ int mp_run(mp_plan *plan, int64_t max_atoms, double target_snr_db,
  * true error reaches target_snr_db (> 0), when max_atoms selections were made
  * (<= 0: L_padded/5), when all coefficients are zero, or when an inner loop
  * made no selection.  The atom log holds every selection; E_after is the
- * inner estimate, reset to the true error at each reset.  Synchronizes with
- * the stream once per reset round.  MP_E_STATE unless called right after
- * mp_analyze; MP_E_ARG for reset_it <= 0 or reset_db > 0. */
+ * inner estimate, reset to the true error at each reset.  reset_it <= 0
+ * selects the default criterion derived from the kernel threshold eps (Sec.
+ * 7): reset_it = ceil(32 / eps) and, unless reset_db < 0 is given,
+ * reset_db = 10 log10(eps).  Synchronizes with the stream once per reset
+ * round.  MP_E_STATE unless called right after mp_analyze; MP_E_ARG for
+ * reset_db > 0. */
 int mp_run_resets(mp_plan *plan, const void *x_dev, int32_t dtype,
                   int64_t max_atoms, double target_snr_db, int64_t reset_it,
                   double reset_db, hipStream_t stream);
 
-/* Copies up to `cap` selected atoms of signal `sig` to out_host, in
- * selection order; *n_out receives the number of atoms selected. */
+/* The solution of Alg. 1 as a list: copies up to `cap` selected atoms of
+ * signal `sig` (system, bin, frame, the adjusted coefficient c~ of Eq.
+ * dualatprod that the solution update adds, and the error estimate after the
+ * selection) to out_host, in selection order; *n_out (may be null) receives
+ * the number of atoms selected.  Waits for the stream of the last mp_run.
+ * MP_E_ARG for a bad plan, signal, cap < 0 or out_host null with cap > 0;
+ * MP_E_HIP if the copy fails. */
 int mp_get_atoms(const mp_plan *plan, int32_t sig, mp_atom *out_host,
                  int64_t cap, int64_t *n_out);
 
-/* Error-estimate curve of signal `sig`: E_0 followed by E_k after each
- * selection; *n_out receives n_atoms + 1. */
+/* Error-estimate curve of signal `sig` (Alg. 1, error update E_k = E_{k-1} -
+ * E~_k with E~_k of Eq. projenfaster): E_0 = ||x||^2 followed by E_k after
+ * each selection, up to `cap` values into E_curve_host; *n_out (may be null)
+ * receives n_atoms + 1.  Waits for the stream of the last mp_run.  Errors as
+ * mp_get_atoms. */
 int mp_get_energy(const mp_plan *plan, int32_t sig, double *E_curve_host,
                   int64_t cap, int64_t *n_out);
 
@@ -251,8 +264,10 @@ int mp_get_residual(const mp_plan *plan, int32_t sig, int32_t w,
 
 /* Synthesis of the selected atoms of signal `sig` (Eq. idgtreal): pairs add
  * 2 Re(c d), DC and Nyquist atoms add Re(c d).  y_dev receives L_padded
- * samples of type dtype (MP_DTYPE_F32 or MP_DTYPE_F64); accumulation is
- * FP64. */
+ * samples of type dtype (MP_DTYPE_F32 or MP_DTYPE_F64: the output type is an
+ * argument so that FP32 plans can return an FP64 synthesis); accumulation is
+ * FP64.  MP_E_ARG for a bad plan, signal, dtype or null y_dev; MP_E_STATE
+ * before mp_analyze. */
 int mp_resynth(const mp_plan *plan, int32_t sig, void *y_dev, int32_t dtype,
                hipStream_t stream);
 
@@ -271,8 +286,13 @@ int mp_get_kernel(const mp_plan *plan, int32_t w, int32_t v, double *re_host,
 /* Counters and device timings of the last mp_analyze / mp_run. */
 int mp_get_stats(const mp_plan *plan, mp_stats *out);
 
+/* Releases the plan and every buffer it owns (the C module's final call,
+ * Sec. 7); waits for the plan's last stream and the device first.  MP_E_ARG
+ * for a null plan. */
 int mp_plan_destroy(mp_plan *plan);
 
+/* Text of a return code (the C module's functions return integer error
+ * codes, Sec. 7); a static string, never null. */
 const char *mp_strerror(int code);
 
 #ifdef __cplusplus

@@ -161,38 +161,40 @@ void make_window(int type, int gl, int a, int M, std::vector<double>& g) {
   for (auto& v : g) v *= s;
 }
 
+void dfree(void* q) { (void)hipFree(q); }
+
 void free_plan(mp_plan* p) {
   if (!p) return;
-  hipFree(p->d_dicts);
-  hipFree(p->d_pairs);
-  hipFree(p->d_sigs);
-  hipFree(p->d_state);
-  hipFree(p->d_epart);
-  hipFree(p->d_win64);
-  hipFree(p->d_win32);
-  hipFree(p->d_tw64);
-  hipFree(p->d_tw32);
-  hipFree(p->d_tab64);
-  hipFree(p->d_tab32);
-  hipFree(p->d_gam64);
-  hipFree(p->d_gam32);
-  hipFree(p->d_root64);
-  hipFree(p->d_root32);
-  hipFree(p->d_planes);
-  hipFree(p->d_leaves);
-  hipFree(p->d_atoms);
-  hipFree(p->d_order);
-  hipFree(p->d_queue);
-  for (auto& f : p->d_fprefix) hipFree(f);
-  hipFree(p->d_acc);
-  hipFree(p->d_res);
-  hipFree(p->d_roff);
-  hipFree(p->d_sigs_res);
-  hipFree(p->d_active);
-  for (auto t : p->d_dft1) hipFree(t);
-  for (auto t : p->d_dft2) hipFree(t);
+  dfree(p->d_dicts);
+  dfree(p->d_pairs);
+  dfree(p->d_sigs);
+  dfree(p->d_state);
+  dfree(p->d_epart);
+  dfree(p->d_win64);
+  dfree(p->d_win32);
+  dfree(p->d_tw64);
+  dfree(p->d_tw32);
+  dfree(p->d_tab64);
+  dfree(p->d_tab32);
+  dfree(p->d_gam64);
+  dfree(p->d_gam32);
+  dfree(p->d_root64);
+  dfree(p->d_root32);
+  dfree(p->d_planes);
+  dfree(p->d_leaves);
+  dfree(p->d_atoms);
+  dfree(p->d_order);
+  dfree(p->d_queue);
+  for (auto& f : p->d_fprefix) dfree(f);
+  dfree(p->d_acc);
+  dfree(p->d_res);
+  dfree(p->d_roff);
+  dfree(p->d_sigs_res);
+  dfree(p->d_active);
+  for (auto t : p->d_dft1) dfree(t);
+  for (auto t : p->d_dft2) dfree(t);
   if (p->ev_valid)
-    for (auto& e : p->ev) hipEventDestroy(e);
+    for (auto& e : p->ev) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -246,7 +248,7 @@ int ensure_cap(mp_plan* p, int64_t K, hipStream_t st) {
   AtomRec* na = nullptr;
   if (hipMalloc((void**)&na, sizeof(AtomRec) * (size_t)total) != hipSuccess) return MP_E_NOMEM;
   if (hipStreamSynchronize(st) != hipSuccess) {
-    hipFree(na);
+    dfree(na);
     return MP_E_HIP;
   }
   int64_t base = 0;
@@ -255,7 +257,7 @@ int ensure_cap(mp_plan* p, int64_t K, hipStream_t st) {
     if (p->hs[s].cap > 0 &&
         hipMemcpy(na + base, p->d_atoms + p->hs[s].atom_base, sizeof(AtomRec) * (size_t)p->hs[s].cap,
                   hipMemcpyDeviceToDevice) != hipSuccess) {
-      hipFree(na);
+      dfree(na);
       return MP_E_HIP;
     }
     ns[s].atom_base = base;
@@ -263,10 +265,10 @@ int ensure_cap(mp_plan* p, int64_t K, hipStream_t st) {
     base += caps[s];
   }
   if (hipMemcpy(p->d_sigs, ns.data(), sizeof(SigDev) * ns.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(na);
+    dfree(na);
     return MP_E_HIP;
   }
-  hipFree(p->d_atoms);
+  dfree(p->d_atoms);
   p->d_atoms = na;
   p->hs = ns;
   p->total_cap = total;
@@ -281,7 +283,7 @@ const char* mp_strerror(int code) {
   switch (code) {
     case MP_OK: return "ok";
     case MP_E_ARG: return "invalid argument";
-    case MP_E_GRID: return "incompatible Gabor systems (a or M not nested, M/a not integer, M not a power of two, gl odd or gl > M)";
+    case MP_E_GRID: return "unsupported Gabor system (M not a power of two, gl odd or gl > 8 M)";
     case MP_E_LEN: return "signal length too short for the kernels (padded L < gl_v + gl_w)";
     case MP_E_NOMEM: return "out of memory";
     case MP_E_HIP: return "HIP runtime error";
@@ -363,8 +365,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       for (int v = 0; v < W; ++v) need = std::max<int64_t>(need, dicts[w].gl + dicts[v].gl);
     }
     // tree group size.  FP64: keep the group nodes within 32 KiB of LDS.
-    // FP32: 256 leaves (128 on request through MPG_GL=128) if the group keys
-    // fit the LDS.
+    // FP32: 256 leaves (128 with MP_SCHED_G128) if the group keys fit the LDS.
     {
       auto groups_max = [&](int G) {
         int64_t m = 0;
@@ -394,13 +395,9 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
         }
       } else {
         // 768 threads (12 waves) unless the group keys and the owners'
-        // scratch only fit the LDS with 512 (or MPG_NT=512 asks for it)
+        // scratch only fit the LDS with 512 (or MP_SCHED_NT512 asks for it)
         p->G = 0;
-        int gpref = (flags & MP_SCHED_G128) ? 128 : 256, ntpref = (flags & MP_SCHED_NT512) ? 512 : 768;
-        if (const char* e = getenv("MPG_GL"))
-          if (atoi(e) == 128) gpref = 128;
-        if (const char* e = getenv("MPG_NT"))
-          if (atoi(e) == 512) ntpref = 512;
+        const int gpref = (flags & MP_SCHED_G128) ? 128 : 256, ntpref = (flags & MP_SCHED_NT512) ? 512 : 768;
         for (int nt : {768, 512}) {
           if (nt > ntpref) continue;
           for (int G : {128, 256}) {
@@ -756,11 +753,7 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     p->ev_valid = true;
 
     // launch shape of the MP loop (FP32: chosen with the group size above)
-    if (p->f64) {
-      p->nt = 512;
-      if (const char* e = getenv("MPG_NT"))
-        if (atoi(e) == 256) p->nt = 256;
-    }
+    if (p->f64) p->nt = 512;
     p->shmem = mp_shmem_bytes(p->f64, p->nt, p->G, p->n_groups_max);
     if (p->shmem == 0 || p->shmem > 160 * 1024) {
       rc = MP_E_LIMIT;
@@ -769,27 +762,27 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
     p->grid = std::min(batch, 2 * prop.multiProcessorCount);
     HCHK(hipStreamSynchronize(st));
   }
-  for (auto t : ptab64) hipFree(t);
-  for (auto t : ptab32) hipFree(t);
-  hipFree(d_full);
-  hipFree(d_roots);
-  hipFree(d_box);
-  hipFree(d_max);
-  hipStreamDestroy(st);
+  for (auto t : ptab64) dfree(t);
+  for (auto t : ptab32) dfree(t);
+  dfree(d_full);
+  dfree(d_roots);
+  dfree(d_box);
+  dfree(d_max);
+  (void)hipStreamDestroy(st);
   *out = p;
   return MP_OK;
 
 fail:
   if (st) {
-    hipStreamSynchronize(st);
-    hipStreamDestroy(st);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
   }
-  for (auto t : ptab64) hipFree(t);
-  for (auto t : ptab32) hipFree(t);
-  hipFree(d_full);
-  hipFree(d_roots);
-  hipFree(d_box);
-  hipFree(d_max);
+  for (auto t : ptab64) dfree(t);
+  for (auto t : ptab32) dfree(t);
+  dfree(d_full);
+  dfree(d_roots);
+  dfree(d_box);
+  dfree(d_max);
   free_plan(p);
   return rc;
 }
@@ -859,6 +852,7 @@ int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream)
   const void* win = r64 ? (const void*)p->d_win64 : (const void*)p->d_win32;
   HCHK(hipEventRecord(p->ev[0], stream));
   HCHK(launch_energy(x_dev, dtype, p->d_sigs, p->batch, p->d_epart, p->d_state, stream));
+  HCHK(hipEventRecord(p->ev[5], stream));  // the DGT kernels alone: ev[5] -> ev[1]
   for (int w = 0; w < p->W; ++w) {
     const DictDev& D = p->hd[w];
     const void* tw = p->dft_fmt >= 0 ? (const void*)(p->d_tw32 + D.tw_off)
@@ -950,9 +944,17 @@ int mp_signal_info_get(const mp_plan* p, int32_t sig, mp_signal_info* out) {
 
 int mp_run_resets(mp_plan* p, const void* x_dev, int32_t dtype, int64_t max_atoms, double target_snr_db,
                   int64_t reset_it, double reset_db, hipStream_t stream) {
-  if (!p || !x_dev || (dtype != MP_DTYPE_F32 && dtype != MP_DTYPE_F64) || reset_it <= 0 || !(reset_db <= 0.0))
-    return MP_E_ARG;
+  if (!p || !x_dev || (dtype != MP_DTYPE_F32 && dtype != MP_DTYPE_F64) || !(reset_db <= 0.0)) return MP_E_ARG;
   if (!p->analyzed || p->ran) return MP_E_STATE;
+  if (reset_it <= 0) {
+    // default reset criterion derived from the kernel threshold (Sec. 7, the
+    // 'reset' flag; the paper does not print its formula): at most
+    // ceil(32 / eps) selections per round (the schedule of Sec. 6.1's second
+    // experiment at eps = 1e-4 and 1e-3), and a reset once the estimate has
+    // fallen by the factor eps below the error at the last reset
+    reset_it = p->eps > 0.0 ? (int64_t)std::ceil(32.0 / p->eps) : ((int64_t)1 << 62);
+    if (reset_db == 0.0 && p->eps > 0.0) reset_db = 10.0 * std::log10(p->eps);
+  }
   int rc = ensure_cap(p, max_atoms, stream);
   if (rc) return rc;
   if (!p->d_res) {
@@ -1121,15 +1123,15 @@ int mp_get_stats(const mp_plan* p, mp_stats* out) {
   }
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, p->ev[0], p->ev[2]) == hipSuccess) out->analyze_ms = ms;
-  if (hipEventElapsedTime(&ms, p->ev[0], p->ev[1]) == hipSuccess) out->dgt_ms = ms;
+  if (hipEventElapsedTime(&ms, p->ev[5], p->ev[1]) == hipSuccess) out->dgt_ms = ms;
   if (p->ran && hipEventElapsedTime(&ms, p->ev[3], p->ev[4]) == hipSuccess) out->loop_ms = ms;
   return MP_OK;
 }
 
 int mp_plan_destroy(mp_plan* p) {
   if (!p) return MP_E_ARG;
-  if (p->last_stream) hipStreamSynchronize(p->last_stream);
-  hipDeviceSynchronize();
+  if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
+  (void)hipDeviceSynchronize();
   free_plan(p);
   return MP_OK;
 }

@@ -2532,7 +2532,7 @@ template <typename R, int NT, int SLOTS>
 static hipError_t launch_mp_t(const MPArgs& a, int grid, bool preload, hipStream_t st) {
   const size_t sh = mp_lds_bytes<R, NT, SLOTS>(a.n_groups_max, preload);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  (void)hipFuncSetAttribute((const void*)k_mp<R, NT, SLOTS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  CHK(hipFuncSetAttribute((const void*)k_mp<R, NT, SLOTS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
   k_mp<R, NT, SLOTS><<<grid, NT, sh, st>>>(a);
   return hipGetLastError();
 }
@@ -2541,8 +2541,8 @@ template <int NT, int SLOTS, int GL>
 static hipError_t launch_mp32_t(const MPArgs& a, int grid, hipStream_t st) {
   const size_t sh = mp32_lds_bytes<NT, GL>(a.n_groups_max);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  (void)hipFuncSetAttribute((const void*)k_mp32<NT, SLOTS, GL>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sh);
+  CHK(hipFuncSetAttribute((const void*)k_mp32<NT, SLOTS, GL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)sh));
   k_mp32<NT, SLOTS, GL><<<grid, NT, sh, st>>>(a);
   return hipGetLastError();
 }
@@ -2551,8 +2551,7 @@ static hipError_t launch_mp32_t(const MPArgs& a, int grid, hipStream_t st) {
 size_t mp_shmem_bytes(bool f64, int nt, int G, int n_groups_max) {
   if (f64) {
     const bool preload = G == GLEAVES;
-    return nt == 256 ? mp_lds_bytes<double, 256, 4>(n_groups_max, preload)
-                     : mp_lds_bytes<double, 512, 4>(n_groups_max, preload);
+    return nt == 512 ? mp_lds_bytes<double, 512, 4>(n_groups_max, preload) : 0;
   }
   if (nt != 512 && nt != 768) return 0;
   if (G == 128) return nt == 768 ? mp32_lds_bytes<768, 128>(n_groups_max) : mp32_lds_bytes<512, 128>(n_groups_max);
@@ -2565,7 +2564,7 @@ hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st
   CHK(hipGetLastError());
   if (f64) {
     const bool preload = a.G == GLEAVES;
-    if (nt == 256) return launch_mp_t<double, 256, 4>(a, grid, preload, st);
+    if (nt != 512) return hipErrorInvalidValue;
     return launch_mp_t<double, 512, 4>(a, grid, preload, st);
   }
   if (a.G == 128) {

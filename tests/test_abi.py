@@ -34,7 +34,7 @@ def test_strerror_and_argument_errors_without_gpu():
     from paper_2202_12380_amd import mpg
     L = mpg.lib()
     assert L.mp_strerror(0) == b"ok"
-    assert b"incompatible" in L.mp_strerror(mpg.MP_E_GRID)
+    assert b"unsupported Gabor system" in L.mp_strerror(mpg.MP_E_GRID)
     cases = [
         ([(0, 64, 16, 64), (0, 64, 24, 96)], [1024], 1e-4, 0, mpg.MP_E_GRID),   # M not a power of 2
         ([(0, 1024, 16, 64)], [4096], 1e-4, 0, mpg.MP_E_GRID),                  # gl > 8 M
