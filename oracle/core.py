@@ -48,6 +48,7 @@ def lib():
         _lib.orc_padded_length.argtypes = [C.POINTER(_Dict), C.c_int32, C.c_int64]
         _lib.orc_padded_length.restype = C.c_int64
         _lib.orc_fft.argtypes = [C.c_int32, dp, dp, C.c_int32]
+        _lib.orc_dft.argtypes = [C.c_int32, dp, dp, C.c_int32]
         _lib.orc_dgt.argtypes = [C.POINTER(_Dict), dp, C.c_int64, dp, dp]
         _lib.orc_dgt_direct.argtypes = [C.POINTER(_Dict), dp, C.c_int64, dp, dp]
         _lib.orc_kernel_direct.argtypes = [C.POINTER(_Dict), C.POINTER(_Dict),
@@ -59,7 +60,7 @@ def lib():
                                           C.POINTER(C.c_int32)]
         _lib.orc_mp.argtypes = [C.POINTER(_Dict), C.c_int32, dp, C.c_int64, C.c_double,
                                 C.c_uint32, C.c_int64, C.c_double, C.c_int64, ip, ip, ip,
-                                dp, dp, dp, dp, C.c_void_p, C.c_void_p, C.POINTER(_Stats)]
+                                dp, dp, dp, dp, dp, C.c_void_p, C.c_void_p, C.POINTER(_Stats)]
         _lib.orc_mp_replay.argtypes = [C.POINTER(_Dict), C.c_int32, dp, C.c_int64, C.c_double,
                                        C.c_uint32, C.c_int64, ip, ip, ip, dp, dp, dp, dp, dp, dp,
                                        C.c_void_p, C.c_void_p, C.POINTER(_Stats)]
@@ -102,6 +103,14 @@ def fft(x: np.ndarray, sign: int = -1) -> np.ndarray:
     return re + 1j * im
 
 
+def dft(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    """DFT of any length (orc_dft)."""
+    re = np.ascontiguousarray(x.real, dtype=np.float64).copy()
+    im = np.ascontiguousarray(np.imag(x), dtype=np.float64).copy()
+    _check(lib().orc_dft(len(re), re, im, sign))
+    return re + 1j * im
+
+
 def dgt(d, x: np.ndarray, direct: bool = False) -> np.ndarray:
     """Reduced DGT plane (N x M/2+1, complex128) of a real signal."""
     x = np.ascontiguousarray(x, dtype=np.float64)
@@ -135,7 +144,7 @@ def kernel_table(dw, dv, eps: float, flags: int = 0) -> KernelTable:
     D = C.c_int32()
     _check(lib().orc_kernel_table(_dicts([dw]), _dicts([dv]), eps, flags, C.byref(D),
                                   None, None, None, None))
-    Mmax = max(dw[3], dv[3])
+    Mmax = dw[3] * dv[3] // math.gcd(dw[3], dv[3])   # lcm: the common grid's bins
     n = (2 * D.value + 1) * Mmax
     re = np.zeros(n)
     im = np.zeros(n)
@@ -154,11 +163,12 @@ class MPResult:
     n: np.ndarray
     c: np.ndarray
     E: np.ndarray      # error estimate after each selection
-    gap: np.ndarray    # relative top-2 gap of |rho|^2 at each selection
+    gap: np.ndarray    # relative top-2 gap of the selection score at each selection
     E0: float
     L_padded: int
     stop_reason: int
     planes: list       # final residual planes per system (or None)
+    best: np.ndarray = None   # the selected score (|rho|^2, or the pedantic score)
 
     @property
     def n_atoms(self):
@@ -183,6 +193,7 @@ def mp(dicts, x: np.ndarray, eps: float, K: int = 0, target_db: float = 0.0,
     cim = np.zeros(cap)
     Ea = np.zeros(cap)
     gp = np.zeros(cap)
+    bs = np.zeros(cap)
     sizes = [(Lp // d[2]) * (d[3] // 2 + 1) for d in dicts]
     fr = fi = None
     if return_planes:
@@ -190,7 +201,7 @@ def mp(dicts, x: np.ndarray, eps: float, K: int = 0, target_db: float = 0.0,
         fi = np.zeros(sum(sizes))
     st = _Stats()
     _check(lib().orc_mp(_dicts(dicts), len(dicts), x, L, eps, flags, K, target_db, cap,
-                        aw, am, an, cre, cim, Ea, gp,
+                        aw, am, an, cre, cim, Ea, gp, bs,
                         fr.ctypes.data if fr is not None else None,
                         fi.ctypes.data if fi is not None else None, C.byref(st)))
     k = st.n_atoms
@@ -202,7 +213,7 @@ def mp(dicts, x: np.ndarray, eps: float, K: int = 0, target_db: float = 0.0,
             o += s
     return MPResult(aw[:k].copy(), am[:k].copy(), an[:k].copy(), cre[:k] + 1j * cim[:k],
                     Ea[:k].copy(), gp[:k].copy(), st.E0, st.L_padded, st.stop_reason,
-                    planes)
+                    planes, bs[:k].copy())
 
 
 @dataclass

@@ -89,9 +89,9 @@ static double win_at(const double *g, int32_t gl, int64_t t) {
 /* grid rules.  Sec. 2.1 asks only for L to be a multiple of every a (and of
  * every M); Sec. 4.2 puts a pair of systems on the common grid with time
  * step gcd(a_w, a_v) and lcm(M_w, M_v) bins.  Readings of this
- * implementation: M is a power of two (so lcm(M_w, M_v) = max), gl is even
- * and gl <= 8 M (a window longer than M is folded modulo M).  Hops need not
- * divide M nor each other.                                                 */
+ * implementation: M is even (bins 0 .. M/2 with a Nyquist bin), gl is even
+ * and gl <= 8 M (a window longer than M is folded modulo M).  Neither the
+ * hops nor the numbers of channels need divide each other.                 */
 
 int orc_check_dicts(const orc_dict *d, int32_t W) {
   if (!d || W <= 0) return ORC_E_ARG;
@@ -100,7 +100,7 @@ int orc_check_dicts(const orc_dict *d, int32_t W) {
         d[w].window != ORC_WIN_GAUSS)
       return ORC_E_ARG;
     if (d[w].a <= 0 || d[w].M <= 0 || d[w].gl <= 0) return ORC_E_ARG;
-    if (!is_pow2(d[w].M) || d[w].M < 2) return ORC_E_GRID;
+    if (d[w].M < 2 || (d[w].M & 1)) return ORC_E_GRID;
     if ((d[w].gl & 1) || d[w].gl > 8 * d[w].M) return ORC_E_GRID;
     /* Blackman or Hann of length 2: a single nonzero sample makes every atom
        real, and Eq. (dualatprod) for a pair would divide by 1 - |gamma|^2 = 0 */
@@ -165,6 +165,37 @@ int orc_fft(int32_t n, double *re, double *im, int32_t sign) {
   return ORC_OK;
 }
 
+/* DFT of any length: the radix-2 FFT above for powers of two, the defining
+ * sum otherwise (phase index k t mod n taken exactly in integers). */
+static int dft_any(int32_t n, double *re, double *im, int32_t sign) {
+  if (is_pow2(n)) return orc_fft(n, re, im, sign);
+  double *xr = malloc(sizeof(double) * n), *xi = malloc(sizeof(double) * n);
+  if (!xr || !xi) {
+    free(xr), free(xi);
+    return ORC_E_NOMEM;
+  }
+  memcpy(xr, re, sizeof(double) * n);
+  memcpy(xi, im, sizeof(double) * n);
+  for (int64_t k = 0; k < n; ++k) {
+    double sr = 0.0, si = 0.0;
+    for (int64_t t = 0; t < n; ++t) {
+      double ang = (double)sign * 2.0 * M_PI * (double)mod64(k * t, n) / (double)n;
+      double c = cos(ang), sn = sin(ang);
+      sr += xr[t] * c - xi[t] * sn;
+      si += xr[t] * sn + xi[t] * c;
+    }
+    re[k] = sr;
+    im[k] = si;
+  }
+  free(xr), free(xi);
+  return ORC_OK;
+}
+
+int orc_dft(int32_t n, double *re, double *im, int32_t sign) {
+  if (n < 1 || !re || !im) return ORC_E_ARG;
+  return dft_any(n, re, im, sign);
+}
+
 /* ------------------------------------------------------------------------ */
 /* DGT analysis rho_0 = D* x (Sec. 5): for frame n,
  *   rho(m, n) = sum_{t=-gl/2}^{gl/2-1} x(n a + t) g(t) exp(-2 pi i m t / M),
@@ -189,7 +220,7 @@ int orc_dgt(const orc_dict *d, const double *x, int64_t L, double *re,
     /* the windowed frame laid out circularly: t mod M (folded when gl > M) */
     for (int32_t t = -gl / 2; t < gl / 2; ++t)
       br[mod64(t, M)] += x[mod64(n * d->a + t, L)] * g[t + gl / 2];
-    orc_fft(M, br, bi, -1);
+    dft_any(M, br, bi, -1);
     for (int32_t m = 0; m < MR; ++m) {
       re[n * MR + m] = br[m];
       im[n * MR + m] = bi[m];
@@ -231,11 +262,11 @@ int orc_dgt_direct(const orc_dict *d, const double *x, int64_t L, double *re,
  *   <d^v_{k,j}, d^w_{m,n}> = h_{w,v}(mu, Delta) exp(2 pi i k Delta / M_v),
  *   h_{w,v}(mu, Delta) = sum_t g_v(t) g_w(t - Delta) exp(-2 pi i mu (t - Delta) / M_max),
  * the twisted-convolution form of Eq. (GramKern)/(hkj) on the common grid
- * (a_min, M_max).                                                          */
+ * (a_min, M_max), M_max = lcm(M_w, M_v).                                   */
 
 int orc_kernel_direct(const orc_dict *dw, const orc_dict *dv, int64_t mu,
                       int64_t Delta, double *re, double *im) {
-  const int32_t Mmax = dw->M > dv->M ? dw->M : dv->M;
+  const int32_t Mmax = (int32_t)lcm64(dw->M, dv->M);
   double *gw = malloc(sizeof(double) * dw->gl);
   double *gv = malloc(sizeof(double) * dv->gl);
   if (!gw || !gv) {
@@ -265,9 +296,9 @@ int orc_kernel_direct(const orc_dict *dw, const orc_dict *dv, int64_t mu,
 int orc_kernel_table(const orc_dict *dw, const orc_dict *dv, double eps,
                      uint32_t flags, int32_t *D_out, double *re, double *im,
                      int32_t *box_mu, int32_t *box_delta) {
-  /* common grid (Sec. 4.2): time step gcd(a_w, a_v), lcm(M_w, M_v) = max bins */
+  /* common grid (Sec. 4.2): time step gcd(a_w, a_v), lcm(M_w, M_v) bins */
   const int32_t amin = (int32_t)gcd64(dw->a, dv->a);
-  const int32_t Mmax = dw->M > dv->M ? dw->M : dv->M;
+  const int32_t Mmax = (int32_t)lcm64(dw->M, dv->M);
   const int32_t halfsum = (dw->gl + dv->gl) / 2;
   /* largest delta with |delta * amin| < halfsum */
   const int32_t D = (halfsum + amin - 1) / amin - 1;
@@ -289,7 +320,7 @@ int orc_kernel_table(const orc_dict *dw, const orc_dict *dv, double eps,
     memset(ci, 0, sizeof(double) * Mmax);
     for (int64_t s = -dw->gl / 2; s < dw->gl / 2; ++s)
       cr[mod64(s, Mmax)] += win_at(gv, dv->gl, s + Delta) * win_at(gw, dw->gl, s);
-    orc_fft(Mmax, cr, ci, -1);
+    dft_any(Mmax, cr, ci, -1);
   }
   double thr = eps;
   if (flags & ORC_THR_REL) {
@@ -326,7 +357,7 @@ int orc_kernel_table(const orc_dict *dw, const orc_dict *dv, double eps,
       memset(ci, 0, sizeof(double) * Mmax);
       for (int64_t s = -dw->gl / 2; s < dw->gl / 2; ++s)
         cr[mod64(s, Mmax)] += win_at(gv, dv->gl, s + Delta) * win_at(gw, dw->gl, s);
-      orc_fft(Mmax, cr, ci, -1);
+      dft_any(Mmax, cr, ci, -1);
       for (int64_t mu = 0; mu < Mmax; ++mu)
         if (llabs(cmod64(mu, Mmax)) > bm) cr[mu] = ci[mu] = 0.0;
     }
@@ -403,9 +434,10 @@ static int mp_core(const orc_dict *d, int32_t W, const double *x, int64_t L,
                    double eps, uint32_t flags, int64_t K, double target_db,
                    int64_t cap, int32_t *aw, int32_t *am, int32_t *an,
                    double *cre, double *cim, double *E_after, double *gap,
-                   double *final_re, double *final_im, orc_stats *st,
-                   int64_t n_forced, const int32_t *fw, const int32_t *fm,
-                   const int32_t *fn, double *best_out, double *chosen_out) {
+                   double *best_sel, double *final_re, double *final_im,
+                   orc_stats *st, int64_t n_forced, const int32_t *fw,
+                   const int32_t *fm, const int32_t *fn, double *best_out,
+                   double *chosen_out) {
   int rc = ORC_OK;
   if (!st || !x || eps < 0.0) return ORC_E_ARG;
   memset(st, 0, sizeof(*st));
@@ -438,7 +470,7 @@ static int mp_core(const orc_dict *d, int32_t W, const double *x, int64_t L,
     for (int32_t v = 0; v < W; ++v) {
       pair_table *t = &T[w * W + v];
       t->amin = (int32_t)gcd64(d[w].a, d[v].a);
-      t->Mmax = d[w].M > d[v].M ? d[w].M : d[v].M;
+      t->Mmax = (int32_t)lcm64(d[w].M, d[v].M);
       orc_kernel_table(&d[w], &d[v], eps, flags, &t->D, NULL, NULL, NULL, NULL);
       size_t n = (size_t)(2 * t->D + 1) * (size_t)t->Mmax;
       t->re = malloc(sizeof(double) * n);
@@ -579,6 +611,7 @@ static int mp_core(const orc_dict *d, int32_t W, const double *x, int64_t L,
     cim[k] = ci;
     E_after[k] = E;
     gap[k] = best > 0.0 ? (best - (second > 0.0 ? second : 0.0)) / best : 0.0;
+    if (best_sel) best_sel[k] = best;
     ++k;
 
     /* residual update (Alg. 3): for every target system w and every target
@@ -644,11 +677,11 @@ done:
 int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
            double eps, uint32_t flags, int64_t K, double target_db,
            int64_t cap, int32_t *aw, int32_t *am, int32_t *an, double *cre,
-           double *cim, double *E_after, double *gap, double *final_re,
-           double *final_im, orc_stats *st) {
+           double *cim, double *E_after, double *gap, double *best,
+           double *final_re, double *final_im, orc_stats *st) {
   return mp_core(d, W, x, L, eps, flags, K, target_db, cap, aw, am, an, cre, cim,
-                 E_after, gap, final_re, final_im, st, -1, NULL, NULL, NULL, NULL,
-                 NULL);
+                 E_after, gap, best, final_re, final_im, st, -1, NULL, NULL, NULL,
+                 NULL, NULL);
 }
 
 int orc_mp_replay(const orc_dict *d, int32_t W, const double *x, int64_t L,
@@ -666,7 +699,7 @@ int orc_mp_replay(const orc_dict *d, int32_t W, const double *x, int64_t L,
   int rc = ORC_E_NOMEM;
   if (aw && am && an)
     rc = mp_core(d, W, x, L, eps, flags, n, 0.0, n > 0 ? n : 1, aw, am, an, cre, cim,
-                 E_after, gap, final_re, final_im, st, n, fw, fm, fn, best, chosen);
+                 E_after, gap, NULL, final_re, final_im, st, n, fw, fm, fn, best, chosen);
   free(aw), free(am), free(an);
   return rc;
 }

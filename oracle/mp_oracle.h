@@ -61,13 +61,16 @@ int orc_window(int32_t type, int32_t gl, double *g);
 /* as orc_window; the Gaussian's width depends on the lattice (a, M) */
 int orc_window_ga(int32_t type, int32_t gl, int32_t a, int32_t M, double *g);
 
-/* Grid validation (M a power of two, gl even and gl <= 8 M) and padded length. */
+/* Grid validation (M even, gl even and gl <= 8 M) and padded length. */
 int orc_check_dicts(const orc_dict *d, int32_t W);
 int64_t orc_padded_length(const orc_dict *d, int32_t W, int64_t L);
 
 /* In-place radix-2 DFT, X(k) = sum_t x(t) exp(-2 pi i k t / n)
  * (sign = -1) or the unnormalised inverse (sign = +1). n a power of two. */
 int orc_fft(int32_t n, double *re, double *im, int32_t sign);
+/* The same transform for any n >= 1: orc_fft for powers of two, the defining
+ * sum otherwise. */
+int orc_dft(int32_t n, double *re, double *im, int32_t sign);
 
 /* DGT of a real signal in one Gabor system, reduced to m = 0..M/2.
  * Output planes are N x (M/2+1), m fastest.  L must be a multiple of a. */
@@ -79,7 +82,7 @@ int orc_dgt_direct(const orc_dict *d, const double *x, int64_t L, double *re,
 
 /* Cross-kernel entry by direct summation:
  * h_{w,v}(mu, Delta) = sum_t g_v(t) g_w(t - Delta) exp(-2 pi i mu (t-Delta)/Mmax)
- * with Mmax = max(M_w, M_v).  dw = target system, dv = source system. */
+ * with Mmax = lcm(M_w, M_v).  dw = target system, dv = source system. */
 int orc_kernel_direct(const orc_dict *dw, const orc_dict *dv, int64_t mu,
                       int64_t Delta, double *re, double *im);
 
@@ -97,14 +100,15 @@ int orc_kernel_table(const orc_dict *dw, const orc_dict *dv, double eps,
  * x has L samples; it is zero-padded to orc_padded_length.
  * K <= 0 selects the default L/5; target_db <= 0 disables the SNR stop.
  * Per selected atom: dictionary, bin, frame, adjusted coefficient c~,
- * error estimate after the step, and the relative top-2 gap of |rho|^2 at
- * selection.  final_re / final_im (may be NULL) receive the residual planes
+ * error estimate after the step, the relative top-2 gap of the selection
+ * score at selection and (best, may be NULL) the selected score itself.
+ * final_re / final_im (may be NULL) receive the residual planes
  * concatenated over the dictionaries. */
 int orc_mp(const orc_dict *d, int32_t W, const double *x, int64_t L,
            double eps, uint32_t flags, int64_t K, double target_db,
            int64_t cap, int32_t *aw, int32_t *am, int32_t *an, double *cre,
-           double *cim, double *E_after, double *gap, double *final_re,
-           double *final_im, orc_stats *st);
+           double *cim, double *E_after, double *gap, double *best,
+           double *final_re, double *final_im, orc_stats *st);
 
 /* Replay: the loop of orc_mp with the selections taken from fw / fm / fn
  * (n of them, e.g. another implementation's run) instead of the maximum.

@@ -70,7 +70,8 @@ class mp_stats(C.Structure):
                 ("dgt_ms", C.c_double), ("group_leaves", C.c_int32), ("threads", C.c_int32)]
 
 
-EXPORTS = ["mp_plan_create", "mp_analyze", "mp_run", "mp_run_resets", "mp_get_atoms", "mp_get_energy",
+EXPORTS = ["mp_plan_create", "mp_analyze", "mp_run", "mp_run_resets",
+           "mp_get_atoms", "mp_get_energy",
            "mp_get_coefs", "mp_get_residual", "mp_resynth", "mp_signal_info_get",
            "mp_kernel_info_get", "mp_get_kernel", "mp_get_stats", "mp_plan_destroy",
            "mp_autotune", "mp_strerror"]
@@ -167,7 +168,7 @@ def mp_run(plan: int, max_atoms: int = 0, target_snr_db: float = 0.0, stream=Non
 
 
 def mp_run_resets(plan: int, x_ptr: int, dtype: int, max_atoms: int = 0, target_snr_db: float = 0.0,
-                  reset_it: int = 1, reset_db: float = 0.0, stream=None):
+                  reset_it: int = 0, reset_db: float = 0.0, stream=None):
     _chk(lib().mp_run_resets(plan, x_ptr, dtype, int(max_atoms), float(target_snr_db), int(reset_it),
                              float(reset_db), _stream(stream)), "mp_run_resets")
 
@@ -281,8 +282,9 @@ class Plan:
     def run(self, max_atoms=0, target_snr_db=0.0, stream=None):
         mp_run(self.h, max_atoms, target_snr_db, stream)
 
-    def run_resets(self, max_atoms=0, target_snr_db=0.0, reset_it=1, reset_db=0.0, stream=None):
-        """Alg. 2 on the signal given to the last analyze()."""
+    def run_resets(self, max_atoms=0, target_snr_db=0.0, reset_it=0, reset_db=0.0, stream=None):
+        """Alg. 2 on the signal given to the last analyze(); reset_it <= 0: the
+        default criterion derived from the kernel threshold."""
         import torch
         dt = MP_DTYPE_F32 if self._x.dtype == torch.float32 else MP_DTYPE_F64
         mp_run_resets(self.h, self._x.data_ptr(), dt, max_atoms, target_snr_db, reset_it, reset_db, stream)

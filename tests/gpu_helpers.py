@@ -21,6 +21,29 @@ def gpu_run(dicts, xs, eps, K=0, snr_db=0.0, flags=0, x_dtype=None):
     return plan, [plan.atoms(s) for s in range(len(xs))]
 
 
+def gpu_run_staged(dicts, xs, eps, stages, snr_db=0.0, flags=0, keep=()):
+    """Runs the HIP path on a batch in stages (mp_run resumed with the
+    selection caps in `stages`, the last one the real cap).  Returns (plan,
+    atoms per signal, checkpoints) where checkpoints[s] maps the selection
+    count of signal s (for s in keep) after each stage to its residual planes."""
+    import torch
+    from paper_2202_12380_amd import mpg
+    f64 = bool(flags & mpg.MP_PREC_F64)
+    x_dtype = torch.float64 if f64 else torch.float32
+    plan = mpg.Plan(dicts, [len(x) for x in xs], eps, flags)
+    x = torch.from_numpy(np.concatenate([np.asarray(v, np.float64) for v in xs])).to(x_dtype).cuda()
+    plan.analyze(x)
+    cps = {s: {} for s in keep}
+    for K in stages:
+        plan.run(K, snr_db)
+        torch.cuda.synchronize()
+        for s in keep:
+            k = int(plan.info(s).n_atoms)
+            if k not in cps[s]:
+                cps[s][k] = planes_of(plan, s, len(dicts))
+    return plan, [plan.atoms(s) for s in range(len(xs))], cps
+
+
 def oracle_run(dicts, x, eps, K=0, snr_db=0.0, flags=0, x_dtype=np.float64, cap=None):
     xv = np.asarray(x).astype(x_dtype).astype(np.float64)
     oflags = 0
@@ -54,32 +77,122 @@ def assert_identical(ga, orc, c_rel=1e-9, e_rel=1e-12):
         assert np.max(np.abs(ga["E_after"] - orc.E)) <= e_rel * orc.E0
 
 
-def fp32_gap_floor(orc, gap_tol=1e-6):
-    """Per-selection top-2 gap below which FP32 may legitimately pick the other
-    coefficient.  A coefficient keeps an absolute rounding error of about
-    u32 |rho_0| sqrt(n) from the n (~16) large early updates that touched it,
-    while its value decays with the residual, |rho_k| ~ |rho_0| sqrt(E_k / E0);
-    the relative error of |rho_k|^2 is then about 2 u32 sqrt(n) sqrt(E0 / E_k)
-    ~ 1e-6 sqrt(E0 / E_k).  The floor is gap_tol at the start and grows as the
-    energy falls (1e-4 at 40 dB)."""
-    E_before = np.concatenate([[orc.E0], orc.E[:-1]]) if orc.n_atoms else np.zeros(0)
-    return np.maximum(gap_tol, 1e-6 * np.sqrt(orc.E0 / np.maximum(E_before, 1e-300)))
+U32 = 2.0 ** -24      # unit roundoff of FP32
+
+# Measured coefficient error of the GPU paths, in units of u32 sqrt(S_0)
+# (S_0 the largest initial selection score): max |rho_gpu - rho_oracle| over
+# all coefficients stays at 1.7 .. 4.3 for the FP32 FFT and FP16-pair
+# analyses and 15 .. 20 for BF16 pairs, from the start of a run to its end
+# (40 dB on audio-like signals, 5e4 selections on white noise; replay tests).
+# The error model used below takes twice the largest measured value.
+C_FP32 = 8.0
+C_BF16 = 32.0
 
 
-def assert_tolerance(ga, orc, gap_tol=1e-6, e_tol=1e-5):
-    """FP32 path: same sequence up to the first selection whose top-2 gap is
-    below the FP32 floor (gap_tol, growing with the energy decay, see
-    fp32_gap_floor), and E within e_tol * ||x||^2 up to there."""
+def fp32_gap_floor(orc, gap_tol=1e-6, c=C_FP32):
+    """Top-2 gap below which the GPU may legitimately select the other
+    coefficient: with an error e <= c u32 sqrt(S_0) on every coefficient, two
+    scores S_k (1 - g) and S_k may swap when g < 4 e / sqrt(S_k) =
+    4 c u32 sqrt(S_0 / S_k) (S_k the selected score at step k).  Reported
+    next to the literal rule; asserted only for the cases that name
+    themselves (floor=True)."""
+    if not orc.n_atoms:
+        return np.zeros(0)
+    S = np.maximum(orc.best, 1e-300)
+    return np.maximum(gap_tol, 4.0 * c * U32 * np.sqrt(S[0] / S))
+
+
+def agreement(ga, orc, gap_tol=1e-6, c=C_FP32):
+    """First difference of the sequences and the first oracle selections
+    whose top-2 gap is below the literal tolerance and below the floor."""
     fm = first_mismatch(ga, orc)
-    small = np.nonzero(orc.gap < fp32_gap_floor(orc, gap_tol))[0]
-    k_gap = int(small[0]) if len(small) else orc.n_atoms
-    if fm < min(len(ga), orc.n_atoms):
+    small = np.nonzero(orc.gap < gap_tol)[0]
+    k_lit = int(small[0]) if len(small) else orc.n_atoms
+    if getattr(orc, "best", None) is None:
+        return fm, k_lit, k_lit
+    small_f = np.nonzero(orc.gap < fp32_gap_floor(orc, gap_tol, c))[0]
+    k_floor = int(small_f[0]) if len(small_f) else orc.n_atoms
+    return fm, k_lit, k_floor
+
+
+def assert_tolerance(ga, orc, gap_tol=1e-6, e_tol=1e-5, floor=False, c=C_FP32):
+    """FP32 path: the same sequence up to the first selection whose oracle
+    top-2 gap is below gap_tol (the literal rule), and E within e_tol ||x||^2
+    up to there.  floor=True (cases named as needing it) asserts the floor of
+    the measured error model instead; both agreement lengths are printed."""
+    fm, k_lit, k_floor = agreement(ga, orc, gap_tol, c)
+    n = min(len(ga), orc.n_atoms)
+    print("agreement: %d of %d (literal %g rule from %d, floor rule from %d)" % (
+        fm, n, gap_tol, k_lit, k_floor))
+    k_gap = k_floor if floor else k_lit
+    if fm < n:
         assert fm >= k_gap, "sequence differs at %d before the first small gap at %d (gap %.3g)" % (
             fm, k_gap, orc.gap[fm])
-    else:
-        # one run may simply be longer (different stop step)
-        assert fm == min(len(ga), orc.n_atoms)
-    upto = min(fm, len(ga), orc.n_atoms)
+    upto = min(fm, n)
     if upto:
         assert np.max(np.abs(ga["E_after"][:upto] - orc.E[:upto])) <= e_tol * orc.E0
     return fm, k_gap
+
+
+def planes_of(plan, s, n_sys):
+    return [plan.residual(s, w).cpu().numpy().astype(np.complex128) for w in range(n_sys)]
+
+
+def replay_check(dicts, x, eps, ga, plane_checkpoints, flags=0, e_tol=1e-5, c_model=C_FP32):
+    """Checks a whole GPU run, past any divergence from the oracle's own
+    sequence: the oracle replays the GPU's selections (orc_mp_replay) and
+      * at each checkpoint k (GPU planes after k selections, given as
+        {k: [plane per system]}) the largest coefficient error
+        e_k = max |rho_gpu - rho_oracle| is measured;
+      * every GPU selection must be a maximum of the oracle's scores up to
+        that error: chosen >= best - 4 sqrt(best) e - 2 e^2, with e the
+        largest error measured at a checkpoint at or after the selection
+        (scores are |rho|^2; an error e per coefficient moves a score by at
+        most 2 |rho| e + e^2, on both sides of the comparison);
+      * the GPU's error estimates follow the replay's within e_tol ||x||^2.
+    c_model: if not None, e_k <= c_model u32 sqrt(S_0) is asserted too (S_0
+    the largest initial score): the error model of fp32_gap_floor.  Returns a
+    report dict."""
+    xv = np.asarray(x, np.float64)
+    oflags = 0
+    if flags & 0x10:
+        oflags |= O.THR_REL
+    if flags & 0x20:
+        oflags |= O.CONJ_GATE_GAMMA
+    if flags & 0x100:
+        oflags |= O.PEDANTIC
+    k_all = len(ga)
+    ks = sorted(plane_checkpoints)
+    assert ks and ks[-1] == k_all, "the last checkpoint must be the end of the run"
+    errs = {}
+    rep = None
+    for k in ks:
+        r = O.mp_replay(dicts, xv, eps, ga["w"][:k], ga["m"][:k], ga["n"][:k], flags=oflags,
+                        return_planes=True)
+        errs[k] = max(float(np.max(np.abs(g - o))) for g, o in zip(plane_checkpoints[k], r.planes))
+        if k == k_all:
+            rep = r
+    S0 = float(rep.best[0]) if k_all else 0.0
+    # error bound per selection: the largest checkpoint error at or after it
+    bound = np.zeros(k_all)
+    prev = 0
+    for k in ks:
+        later = max(errs[q] for q in ks if q >= k)
+        bound[prev:k] = later
+        prev = k
+    slack = rep.best - rep.chosen
+    allowed = 4.0 * np.sqrt(rep.best) * bound + 2.0 * bound ** 2
+    bad = np.nonzero(slack > allowed * (1 + 1e-12) + 1e-300)[0]
+    dE = float(np.max(np.abs(ga["E_after"] - rep.E))) / rep.E0 if k_all else 0.0
+    c_meas = {k: errs[k] / (U32 * np.sqrt(S0)) for k in ks} if S0 > 0 else {}
+    report = dict(n=k_all, errors=errs, c_measured=c_meas, invalid=len(bad),
+                  first_invalid=int(bad[0]) if len(bad) else -1,
+                  worst_ratio=float(np.max(slack / np.maximum(allowed, 1e-300))) if k_all else 0.0,
+                  max_dE_over_E0=dE)
+    print("replay:", report)
+    assert len(bad) == 0, "GPU selection %d is not a maximum within the measured error (%s)" % (
+        bad[0], report)
+    assert dE <= e_tol, report
+    if c_model is not None:
+        assert all(v <= c_model for v in c_meas.values()), report
+    return report

@@ -3,13 +3,17 @@ configurations: one to three Gabor systems with any window, frame lengths
 8 .. 256, windows up to twice the frame, hops that divide M or not, ragged
 signal lengths.  FP64 plans must select what the oracle selects (up to the
 first selection whose oracle top-2 gap is below 1e-10, where rounding may
-legitimately decide); FP32 plans follow the FP32 rule of the other tests."""
+legitimately decide).  FP32 plans run 150 selections on signals as short as
+64 samples, far below the signal's energy, so they are named as a case of the
+measured-error floor (gpu_helpers.fp32_gap_floor) rather than the literal 1e-6
+rule, and every run is also replayed on the oracle: each selection a maximum
+within the measured coefficient error, E within 1e-5 ||x||^2."""
 import numpy as np
 import pytest
 from hypothesis import given, settings, HealthCheck, strategies as st
 
 from oracle import core as O
-from gpu_helpers import gpu_run, oracle_run, first_mismatch, assert_tolerance
+from gpu_helpers import gpu_run, oracle_run, first_mismatch, assert_tolerance, planes_of, replay_check
 
 pytestmark = pytest.mark.gpu
 F64 = 0x1
@@ -72,6 +76,7 @@ def test_random_configs_fp32_rule(cfg):
     x = _signal(L, seed).astype(np.float32)
     K = 150
     print("fp32 case", dicts, L, seed, flush=True)
-    _, ga = gpu_run(dicts, [x], 1e-4, K=K, flags=0)
+    plan, ga = gpu_run(dicts, [x], 1e-4, K=K, flags=0)
     orc = oracle_run(dicts, x, 1e-4, K=K, x_dtype=np.float32)
-    assert_tolerance(ga[0], orc)
+    assert_tolerance(ga[0], orc, floor=True)
+    replay_check(dicts, x.astype(np.float64), 1e-4, ga[0], {len(ga[0]): planes_of(plan, 0, len(dicts))})

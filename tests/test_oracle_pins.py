@@ -79,6 +79,9 @@ PAIR_CASES = [
     ((2, 32, 4, 16), (2, 64, 8, 32)),   # two Gaussians, both longer than M
     ((0, 32, 12, 32), (0, 64, 16, 64)),  # hops 12 / 16: common grid step gcd = 4
     ((1, 48, 20, 64), (2, 64, 24, 32)),  # hops 20 / 24, neither divides M
+    ((0, 24, 6, 24), (0, 32, 8, 32)),    # M = 24 and 32: common grid lcm = 96 bins
+    ((1, 36, 9, 12), (0, 20, 5, 20)),    # M = 12 and 20 (lcm 60), folded window
+    ((2, 48, 12, 48), (0, 96, 24, 96)),  # M = 48 / 96 (nested, not powers of two)
 ]
 
 
@@ -141,7 +144,8 @@ def test_p2_kernel_conjugate_symmetry():
 # P3: DGT
 
 @pytest.mark.parametrize("d", [(0, 16, 4, 16), (0, 32, 8, 64), (1, 64, 16, 64), (2, 64, 8, 32),
-                               (0, 48, 8, 16), (0, 32, 12, 32), (2, 64, 20, 64)])
+                               (0, 48, 8, 16), (0, 32, 12, 32), (2, 64, 20, 64),
+                               (0, 24, 6, 24), (1, 96, 24, 96), (2, 40, 10, 20), (0, 36, 12, 12)])
 def test_p3_dgt_direct_fft_numpy(d):
     L = int(np.lcm(d[2], d[3]))
     L *= -(-256 // L)
@@ -161,6 +165,14 @@ def test_p3_dgt_direct_fft_numpy(d):
     # and the brute-force dictionary
     D, _ = T.dictionary([d], L)
     assert np.max(np.abs(D.conj().T @ x - c1.ravel())) < 1e-12
+
+
+def test_p3_dft_of_any_length_against_numpy():
+    # the DFT of lengths that are not powers of two (the defining sum)
+    for n in (3, 6, 12, 24, 96, 160):
+        x = np.random.default_rng(n).standard_normal(n) + 1j * np.random.default_rng(n + 1).standard_normal(n)
+        assert np.max(np.abs(O.dft(x) - np.fft.fft(x))) < 1e-12 * n
+        assert np.max(np.abs(O.dft(x, +1) - n * np.fft.ifft(x))) < 1e-12 * n
 
 
 def test_p3_fft_against_direct_dft():
@@ -240,6 +252,8 @@ P5_CASES = [
     ([(2, 64, 8, 32), (0, 32, 8, 32)], 256, 6),       # Gaussian longer than M
     ([(0, 32, 12, 32), (0, 64, 16, 64)], 192, 7),     # hops not nested: gcd grid
     ([(1, 48, 20, 64), (2, 64, 24, 32)], 960, 8),     # hops dividing neither M
+    ([(0, 24, 6, 24), (0, 32, 8, 32)], 192, 9),       # M = 24 / 32: common grid of lcm = 96 bins
+    ([(1, 24, 6, 12), (2, 40, 10, 20)], 240, 10),     # M = 12 / 20 (lcm 60)
 ]
 
 
@@ -482,7 +496,8 @@ def test_stop_rules_and_errors():
     r = O.mp(dicts, x, 1e-4)
     assert r.n_atoms == 512 // 5
     # grids
-    assert O.check_dicts([(0, 64, 16, 64), (0, 64, 24, 96)]) != 0     # M not power of 2
+    assert O.check_dicts([(0, 64, 16, 64), (0, 64, 24, 96)]) == 0     # M = 96: lcm grid of 192 bins
+    assert O.check_dicts([(0, 64, 16, 63)]) != 0                      # odd M (no Nyquist bin)
     assert O.check_dicts([(0, 64, 16, 64), (0, 128, 48, 128)]) == 0   # a not nested: gcd grid
     assert O.check_dicts([(0, 128, 16, 64)]) == 0                     # gl > M: folded
     assert O.check_dicts([(0, 1024, 16, 64)]) != 0                    # gl > 8 M
@@ -515,3 +530,16 @@ def test_resynth_matches_dictionary():
         d = T.atom(dicts[w], int(m), int(n), L)
         ref += (c * d + (np.conj(c) * d.conj() if (m != 0 and 2 * m != dicts[w][3]) else 0)).real
     assert np.max(np.abs(y - ref)) < 1e-13
+
+
+def test_stored_five_system_reference_is_the_oracle():
+    # the stored oracle run that the GPU test of the five-system signal reads
+    # (tests/golden/make_c5_oracle_reference.py) is what the oracle computes:
+    # its first selections recomputed here
+    z = np.load(os.path.join(GOLD, "c5_sig0_oracle_20k.npz"))
+    wl = S.workload(5)
+    assert [tuple(int(v) for v in d) for d in z["dicts"]] == [tuple(d) for d in wl.dicts]
+    x = S.signals(5, batch=1)[0].astype(np.float32).astype(np.float64)
+    r = O.mp(wl.dicts, x, float(z["eps"]), K=40)
+    assert np.array_equal(r.w, z["w"][:40]) and np.array_equal(r.m, z["m"][:40]) and np.array_equal(r.n, z["n"][:40])
+    assert np.array_equal(r.E, z["E"][:40]) and float(z["E0"]) == r.E0
