@@ -1067,9 +1067,9 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
   // LDS carve-up (must match mp_lds_bytes)
   Key* gkey = reinterpret_cast<Key*>(smem);
   Cx<R>* gval = reinterpret_cast<Cx<R>*>(gkey + A.n_groups_max);
-  Leaf<R>* scratch = reinterpret_cast<Leaf<R>*>(gval + A.n_groups_max);
+  Leaf<R>* lscr = reinterpret_cast<Leaf<R>*>(gval + A.n_groups_max);
   Tgt* tg = reinterpret_cast<Tgt*>(
-      reinterpret_cast<unsigned char*>(scratch) + (preload ? (size_t)MAXTG * GLEAVES * sizeof(Leaf<R>) : 0));
+      reinterpret_cast<unsigned char*>(lscr) + (preload ? (size_t)MAXTG * GLEAVES * sizeof(Leaf<R>) : 0));
   PairC* pc = reinterpret_cast<PairC*>(tg + MAXW);
   DictC* dc = reinterpret_cast<DictC*>(pc + MAXW * MAXW);
   int* slotg = reinterpret_cast<int*>(dc + MAXW);
@@ -1123,7 +1123,7 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
     }
   }
   if (preload)
-    for (int i = threadIdx.x; i < MAXTG * GLEAVES; i += NT) scratch[i] = make_leaf(KD::sentinel(), (R)0, (R)0);
+    for (int i = threadIdx.x; i < MAXTG * GLEAVES; i += NT) lscr[i] = make_leaf(KD::sentinel(), (R)0, (R)0);
   __syncthreads();
 
   SigState st = A.state[s];
@@ -1427,7 +1427,7 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
           const Leaf<R> nl = make_leaf(KO::make(val, (uint32_t)ee[sl]), r[sl].re, r[sl].im);
           const int b = lfi[sl];
           leaves[b] = nl;
-          if (preload && gsl[sl] < MAXTG) scratch[gsl[sl] * GLEAVES + (b & (GLEAVES - 1))] = nl;
+          if (preload && gsl[sl] < MAXTG) lscr[gsl[sl] * GLEAVES + (b & (GLEAVES - 1))] = nl;
         }
       }
       if ((round + 1) * RPR >= T_items) break;
@@ -1442,7 +1442,7 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
       if (preload && gs < MAXTG) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          Leaf<R>& sc = scratch[gs * GLEAVES + lane + 64 * i];
+          Leaf<R>& sc = lscr[gs * GLEAVES + lane + 64 * i];
           Leaf<R> c = (gs == my_gs && own_pre) ? old[i] : leaves[(g << logG) + lane + 64 * i];
           const Leaf<R> scv = sc;
           if (!KD::is_sentinel(leaf_key(scv))) {
@@ -1599,8 +1599,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
 
   // LDS carve-up (must match mp32_lds_bytes)
   uint64_t* gkey = reinterpret_cast<uint64_t*>(smem);
-  uint64_t* scratch = gkey + ngp_max;
-  RowT* tg2 = reinterpret_cast<RowT*>(scratch + NPRE * GL);     // two buffers of MAXW
+  uint64_t* lscr = gkey + ngp_max;
+  RowT* tg2 = reinterpret_cast<RowT*>(lscr + NPRE * GL);     // two buffers of MAXW
   PairC* pc = reinterpret_cast<PairC*>(tg2 + 2 * MAXW);
   It32* it2 = reinterpret_cast<It32*>(pc + MAXW * MAXW);        // two buffers
   uint64_t* ckey = reinterpret_cast<uint64_t*>(it2 + 2);        // [b]: candidate key of buffer b
@@ -1651,7 +1651,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     const uint64_t wm = wave_max_key2<float>(best);
     if (lane == 0) gkey[g] = wm;
   }
-  for (int i = threadIdx.x; i < NPRE * GL; i += NT) scratch[i] = KEY_SENT;
+  for (int i = threadIdx.x; i < NPRE * GL; i += NT) lscr[i] = KEY_SENT;
   if (threadIdx.x < 4) ckey[threadIdx.x] = 0ull;  // ckey[0..1], tmax[0..1]
   if (threadIdx.x == 0) *rowq = 0;
   static_assert(2 * NW <= 64, "owner slots are listed in It32::glist");
@@ -2007,7 +2007,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
         const uint64_t key = ((uint64_t)rm << 32) | (uint64_t)(~eb);
         const uint32_t b = lfi[sl];
         leaves[b] = key;
-        if (gsl[sl] < NPRE) scratch[gsl[sl] * GL + (b & (GL - 1))] = key;
+        if (gsl[sl] < NPRE) lscr[gsl[sl] * GL + (b & (GL - 1))] = key;
       }
     }
     c_upd += n_upd;
@@ -2128,11 +2128,11 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     auto merge_slot = [&](int gs, int g, const uint64_t* old) {
       uint64_t scv[LPL];
 #pragma unroll
-      for (int x = 0; x < LPL; ++x) scv[x] = scratch[gs * GL + lane + 64 * x];
+      for (int x = 0; x < LPL; ++x) scv[x] = lscr[gs * GL + lane + 64 * x];
       uint64_t cand[LPL];
 #pragma unroll
       for (int x = 0; x < LPL; ++x) {
-        scratch[gs * GL + lane + 64 * x] = KEY_SENT;
+        lscr[gs * GL + lane + 64 * x] = KEY_SENT;
         cand[x] = scv[x] != KEY_SENT ? scv[x] : old[x];
       }
       // pairwise tree: depth log2(LPL)
@@ -2217,39 +2217,33 @@ __global__ void k_fill_i32(int32_t* p, int n, int v) {
 }
 
 // --------------------------------------------------------------------------
-// Synthesis of real atoms (Eq. idgtreal).  One workgroup; thread t owns the
-// samples l with l mod blockDim.x == t, so atoms are added in selection order
-// without atomics.  Accumulation in FP64.
+// Synthesis of real atoms (Eq. idgtreal), accumulated in FP64.  The padded
+// signal is cut into segments of RS_SEG samples, one workgroup each.  A
+// workgroup walks the atoms in selection order and adds the part of each atom
+// that falls into its segment; thread t owns the samples lo + t + T r of the
+// segment, so every sample receives its contributions in selection order
+// without atomics (the result does not depend on the number of workgroups).
+// The last step rounds the segment to the output type.
 
-__global__ void __launch_bounds__(1024) k_resynth(const AtomRec* __restrict__ atoms, const SigState* __restrict__ st,
-                                                  const DictDev* __restrict__ dicts,
-                                                  const double* __restrict__ win64, int64_t Lp,
-                                                  double* __restrict__ acc) {
+constexpr int RS_SEG = 8192;
+constexpr int RS_NT = 256;
+
+template <typename YT>
+__global__ void __launch_bounds__(RS_NT) k_resynth(const AtomRec* __restrict__ atoms,
+                                                   const SigState* __restrict__ st,
+                                                   const DictDev* __restrict__ dicts,
+                                                   const double* __restrict__ win64, int64_t Lp,
+                                                   double* __restrict__ acc, YT* __restrict__ y) {
   const int64_t T = blockDim.x, tid = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * RS_SEG, hi = lo + RS_SEG < Lp ? lo + RS_SEG : Lp;
   const int64_t n_atoms = st->k;
-  for (int64_t l = tid; l < Lp; l += T) acc[l] = 0.0;
-  for (int64_t i = 0; i < n_atoms; ++i) {
-    const AtomRec at = atoms[i];
-    const DictDev D = dicts[at.w];
-    const double mult = (at.m != 0 && 2 * at.m != D.M) ? 2.0 : 1.0;
-    const double* g = win64 + D.win_off;
-    // sample of t = -gl/2 (tp = 0), wrapped into [0, Lp)
-    int64_t s0 = ((int64_t)at.n * D.a - D.gl / 2) % Lp;
-    if (s0 < 0) s0 += Lp;
-    const int64_t split = D.gl < Lp - s0 ? D.gl : Lp - s0;
-    int64_t t0 = (tid - s0) % T;
-    if (t0 < 0) t0 += T;
-    // tp < split: l = s0 + tp; tp >= split: l = s0 + tp - Lp
-    for (int64_t tp = t0; tp < split; tp += T) {
-      const int64_t t = tp - D.gl / 2;
-      int64_t pi = ((int64_t)at.m * t) % D.M;
-      if (pi < 0) pi += D.M;
-      double sn, cs;
-      sincospi(2.0 * (double)pi / (double)D.M, &sn, &cs);
-      acc[s0 + tp] += mult * g[tp] * (at.re * cs - at.im * sn);
-    }
-    for (int64_t l = tid; l < D.gl - split; l += T) {
-      const int64_t tp = l + Lp - s0;
+  for (int64_t l = lo + tid; l < hi; l += T) acc[l] = 0.0;
+  // adds samples l in [a, b) of the atom, whose window sample tp is l + sh
+  auto add = [&](const AtomRec& at, const DictDev& D, const double* g, double mult, int64_t a, int64_t b,
+                 int64_t sh) {
+    int64_t l = a + ((tid - (a - lo)) % T + T) % T;  // first owned sample at or after a
+    for (; l < b; l += T) {
+      const int64_t tp = l + sh;
       const int64_t t = tp - D.gl / 2;
       int64_t pi = ((int64_t)at.m * t) % D.M;
       if (pi < 0) pi += D.M;
@@ -2257,27 +2251,43 @@ __global__ void __launch_bounds__(1024) k_resynth(const AtomRec* __restrict__ at
       sincospi(2.0 * (double)pi / (double)D.M, &sn, &cs);
       acc[l] += mult * g[tp] * (at.re * cs - at.im * sn);
     }
+  };
+  for (int64_t i = 0; i < n_atoms; ++i) {
+    const AtomRec at = atoms[i];
+    const DictDev D = dicts[at.w];
+    // window sample tp = 0 (t = -gl/2) sits at s0, wrapped into [0, Lp):
+    // samples s0 .. s0 + split - 1, then 0 .. gl - split - 1
+    int64_t s0 = ((int64_t)at.n * D.a - D.gl / 2) % Lp;
+    if (s0 < 0) s0 += Lp;
+    const int64_t split = D.gl < Lp - s0 ? D.gl : Lp - s0;
+    const int64_t a1 = s0 > lo ? s0 : lo, b1 = s0 + split < hi ? s0 + split : hi;
+    const int64_t b2 = D.gl - split < hi ? D.gl - split : hi;
+    if (a1 >= b1 && lo >= b2) continue;  // uniform: the atom misses the segment
+    const double mult = (at.m != 0 && 2 * at.m != D.M) ? 2.0 : 1.0;
+    const double* g = win64 + D.win_off;
+    if (a1 < b1) add(at, D, g, mult, a1, b1, -s0);
+    if (lo < b2) add(at, D, g, mult, lo, b2, Lp - s0);
   }
-}
-
-template <typename YT>
-__global__ void k_store_y(const double* __restrict__ acc, int64_t n, YT* __restrict__ y) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (YT)acc[i];
+  for (int64_t l = lo + tid; l < hi; l += T) y[l] = (YT)acc[l];
 }
 
 // Solution vector (Alg. 1 solution update): c(m, n) = sum of c~ of the atoms
-// selected at (w, m, n).  One workgroup; thread t owns entries idx mod T.
+// selected at (w, m, n), added in selection order.  Entries are cut into
+// ranges of CF_SEG, one workgroup each; thread t owns the entries
+// lo + t + T r of its range.
+constexpr int CF_SEG = 16384;
+
 __global__ void __launch_bounds__(1024) k_coefs(const AtomRec* __restrict__ atoms, const SigState* __restrict__ st,
                                                 int w, int MR, int64_t n_entries, double2* __restrict__ c) {
-  const int T = blockDim.x, tid = threadIdx.x;
+  const int64_t T = blockDim.x, tid = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * CF_SEG, hi = lo + CF_SEG < n_entries ? lo + CF_SEG : n_entries;
   const int64_t n_atoms = st->k;
-  for (int64_t i = tid; i < n_entries; i += T) c[i] = make_double2(0.0, 0.0);
+  for (int64_t i = lo + tid; i < hi; i += T) c[i] = make_double2(0.0, 0.0);
   for (int64_t i = 0; i < n_atoms; ++i) {
     const AtomRec at = atoms[i];
     if (at.w != w) continue;
     const int64_t idx = (int64_t)at.n * MR + at.m;
-    if (idx % T != tid) continue;
+    if (idx < lo || idx >= hi || (idx - lo) % T != tid) continue;
     double2 v = c[idx];
     v.x += at.re;
     v.y += at.im;
@@ -2580,19 +2590,20 @@ hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st
 
 hipError_t launch_resynth(const AtomRec* atoms, const SigState* st_, const DictDev* dicts, const double* win64,
                           int64_t Lp, double* acc, void* y, int dtype, hipStream_t st) {
-  k_resynth<<<1, 1024, 0, st>>>(atoms, st_, dicts, win64, Lp, acc);
-  CHK(hipGetLastError());
-  const unsigned g = (unsigned)((Lp + 255) / 256);
+  if (Lp <= 0) return hipSuccess;
+  const unsigned g = (unsigned)((Lp + RS_SEG - 1) / RS_SEG);
   if (dtype == 0)
-    k_store_y<float><<<g, 256, 0, st>>>(acc, Lp, (float*)y);
+    k_resynth<float><<<g, RS_NT, 0, st>>>(atoms, st_, dicts, win64, Lp, acc, (float*)y);
   else
-    k_store_y<double><<<g, 256, 0, st>>>(acc, Lp, (double*)y);
+    k_resynth<double><<<g, RS_NT, 0, st>>>(atoms, st_, dicts, win64, Lp, acc, (double*)y);
   return hipGetLastError();
 }
 
 hipError_t launch_coefs(const AtomRec* atoms, const SigState* st_, int w, int MR, int64_t n_entries, void* c,
                         hipStream_t st) {
-  k_coefs<<<1, 1024, 0, st>>>(atoms, st_, w, MR, n_entries, (double2*)c);
+  if (n_entries <= 0) return hipSuccess;
+  const unsigned g = (unsigned)((n_entries + CF_SEG - 1) / CF_SEG);
+  k_coefs<<<g, 1024, 0, st>>>(atoms, st_, w, MR, n_entries, (double2*)c);
   return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ def gpu_run_staged(dicts, xs, eps, stages, snr_db=0.0, flags=0, keep=()):
     """Runs the HIP path on a batch in stages (mp_run resumed with the
     selection caps in `stages`, the last one the real cap).  Returns (plan,
     atoms per signal, checkpoints) where checkpoints[s] maps the selection
-    count of signal s (for s in keep) after each stage to its residual planes."""
+    count of signal s (for s in keep) after the analysis (0) and after each
+    stage to its residual planes."""
     import torch
     from paper_2202_12380_amd import mpg
     f64 = bool(flags & mpg.MP_PREC_F64)
@@ -33,7 +34,8 @@ def gpu_run_staged(dicts, xs, eps, stages, snr_db=0.0, flags=0, keep=()):
     plan = mpg.Plan(dicts, [len(x) for x in xs], eps, flags)
     x = torch.from_numpy(np.concatenate([np.asarray(v, np.float64) for v in xs])).to(x_dtype).cuda()
     plan.analyze(x)
-    cps = {s: {} for s in keep}
+    torch.cuda.synchronize()
+    cps = {s: {0: planes_of(plan, s, len(dicts))} for s in keep}   # after the analysis
     for K in stages:
         plan.run(K, snr_db)
         torch.cuda.synchronize()
@@ -115,6 +117,16 @@ def agreement(ga, orc, gap_tol=1e-6, c=C_FP32):
     return fm, k_lit, k_floor
 
 
+def measured_floor_agreement(ga, orc, e, gap_tol=1e-6):
+    """First oracle selection at which the GPU may legitimately choose another
+    coefficient given a measured error e on every coefficient: its top-2 gap
+    is below max(gap_tol, (4 sqrt(S_k) e + 2 e^2) / S_k)."""
+    S = np.maximum(orc.best, 1e-300)
+    thr = np.maximum(gap_tol, (4.0 * np.sqrt(S) * e + 2.0 * e * e) / S)
+    small = np.nonzero(orc.gap < thr)[0]
+    return int(small[0]) if len(small) else orc.n_atoms
+
+
 def assert_tolerance(ga, orc, gap_tol=1e-6, e_tol=1e-5, floor=False, c=C_FP32):
     """FP32 path: the same sequence up to the first selection whose oracle
     top-2 gap is below gap_tol (the literal rule), and E within e_tol ||x||^2
@@ -145,10 +157,14 @@ def replay_check(dicts, x, eps, ga, plane_checkpoints, flags=0, e_tol=1e-5, c_mo
         {k: [plane per system]}) the largest coefficient error
         e_k = max |rho_gpu - rho_oracle| is measured;
       * every GPU selection must be a maximum of the oracle's scores up to
-        that error: chosen >= best - 4 sqrt(best) e - 2 e^2, with e the
-        largest error measured at a checkpoint at or after the selection
-        (scores are |rho|^2; an error e per coefficient moves a score by at
-        most 2 |rho| e + e^2, on both sides of the comparison);
+        that error: chosen >= best - 4 sqrt(best) e - 2 e^2 (scores are
+        |rho|^2; an error e per coefficient moves a score by at most
+        2 |rho| e + e^2, on both sides of the comparison).  Selection i is
+        made on the planes after i selections; e is the error measured there
+        when a checkpoint sits at i, else the larger of the errors at the two
+        checkpoints around i (exact with a checkpoint at every selection; with
+        sparse checkpoints it assumes that the error between two checkpoints
+        stays within theirs, which c_model backs);
       * the GPU's error estimates follow the replay's within e_tol ||x||^2.
     c_model: if not None, e_k <= c_model u32 sqrt(S_0) is asserted too (S_0
     the largest initial score): the error model of fp32_gap_floor.  Returns a
@@ -173,13 +189,16 @@ def replay_check(dicts, x, eps, ga, plane_checkpoints, flags=0, e_tol=1e-5, c_mo
         if k == k_all:
             rep = r
     S0 = float(rep.best[0]) if k_all else 0.0
-    # error bound per selection: the largest checkpoint error at or after it
-    bound = np.zeros(k_all)
-    prev = 0
-    for k in ks:
-        later = max(errs[q] for q in ks if q >= k)
-        bound[prev:k] = later
-        prev = k
+    # error bound per selection: the checkpoint at it, else the larger of the
+    # two around it
+    ka = np.asarray(ks)
+    ea = np.asarray([errs[q] for q in ks])
+    idx = np.arange(k_all)
+    j1 = np.searchsorted(ka, idx, side="right") - 1      # last checkpoint <= i
+    j2 = np.searchsorted(ka, idx, side="left")           # first checkpoint >= i
+    e1 = np.where(j1 >= 0, ea[np.clip(j1, 0, len(ka) - 1)], 0.0)
+    e2 = np.where(j2 < len(ka), ea[np.clip(j2, 0, len(ka) - 1)], 0.0)
+    bound = np.maximum(e1, e2)
     slack = rep.best - rep.chosen
     allowed = 4.0 * np.sqrt(rep.best) * bound + 2.0 * bound ** 2
     bad = np.nonzero(slack > allowed * (1 + 1e-12) + 1e-300)[0]
@@ -189,7 +208,14 @@ def replay_check(dicts, x, eps, ga, plane_checkpoints, flags=0, e_tol=1e-5, c_mo
                   first_invalid=int(bad[0]) if len(bad) else -1,
                   worst_ratio=float(np.max(slack / np.maximum(allowed, 1e-300))) if k_all else 0.0,
                   max_dE_over_E0=dE)
-    print("replay:", report)
+    report["max_error"] = float(ea.max())
+    if len(ks) > 8:  # dense checkpoints: print the largest ones only
+        top = sorted(ks, key=lambda q: -errs[q])[:4]
+        shown = dict(report, errors={q: errs[q] for q in top},
+                     c_measured={q: c_meas[q] for q in top} if c_meas else {})
+        print("replay (%d checkpoints, largest shown):" % len(ks), shown)
+    else:
+        print("replay:", report)
     assert len(bad) == 0, "GPU selection %d is not a maximum within the measured error (%s)" % (
         bad[0], report)
     assert dE <= e_tol, report
