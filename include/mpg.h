@@ -271,6 +271,23 @@ int mp_get_residual(const mp_plan *plan, int32_t sig, int32_t w,
 int mp_resynth(const mp_plan *plan, int32_t sig, void *y_dev, int32_t dtype,
                hipStream_t stream);
 
+/* Allocation-free synthesis, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, output and errors as mp_resynth, and the same
+ * kernels; the FP64 accumulator is not a plan buffer but a static device
+ * array of MP_STATIC_RESYNTH_MAX samples that the library holds on every
+ * device it runs on until the process ends (its address is looked up once
+ * per device, on the first call there).  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).  L_padded of the signal
+ * above MP_STATIC_RESYNTH_MAX: MP_E_LIMIT.  The call runs on the plan's
+ * device.  All calls on one device share the array (each call clears the
+ * part it uses before accumulating), so calls that overlap in time on one
+ * device, on any streams or plans, race and must be serialised by the
+ * caller. */
+#define MP_STATIC_RESYNTH_MAX ((int64_t)1 << 22)
+int mp_resynth_static(const mp_plan *plan, int32_t sig, void *y_dev, int32_t dtype,
+                      hipStream_t stream);
+
 int mp_signal_info_get(const mp_plan *plan, int32_t sig, mp_signal_info *out);
 
 /* Pair (target w, source v) kernel geometry, and the FP64 box table

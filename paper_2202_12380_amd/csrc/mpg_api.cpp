@@ -47,6 +47,7 @@ hipError_t launch_resynth(const AtomRec* atoms, const SigState* st_, const DictD
                           hipStream_t st);
 hipError_t launch_coefs(const AtomRec* atoms, const SigState* st_, int w, int MR, int64_t n_entries,
                         void* c, hipStream_t st);
+hipError_t static_scratch(double** out, int64_t* n_out);
 }  // namespace mpg
 
 using namespace mpg;
@@ -1085,6 +1086,28 @@ int mp_resynth(const mp_plan* p, int32_t sig, void* y_dev, int32_t dtype, hipStr
                      dtype, stream) != hipSuccess)
     return MP_E_HIP;
   return MP_OK;
+}
+
+int mp_resynth_static(const mp_plan* p, int32_t sig, void* y_dev, int32_t dtype, hipStream_t stream) {
+  if (!p || !y_dev || sig < 0 || sig >= p->batch || (dtype != MP_DTYPE_F32 && dtype != MP_DTYPE_F64))
+    return MP_E_ARG;
+  if (!p->analyzed) return MP_E_STATE;
+  const SigDev& S = p->hs[sig];
+  if (S.Lp > MP_STATIC_RESYNTH_MAX) return MP_E_LIMIT;
+  static_assert(MP_STATIC_RESYNTH_MAX == STATIC_RESYNTH_MAX, "limit in the header and the array agree");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return MP_E_HIP;
+  if (cur != p->device && hipSetDevice(p->device) != hipSuccess) return MP_E_HIP;
+  double* acc = nullptr;
+  int64_t cap = 0;
+  int rc = MP_OK;
+  if (static_scratch(&acc, &cap) != hipSuccess || cap < S.Lp)
+    rc = MP_E_HIP;
+  else if (launch_resynth(p->d_atoms + S.atom_base, p->d_state + sig, p->d_dicts, p->d_win64, S.Lp, acc, y_dev,
+                          dtype, stream) != hipSuccess)
+    rc = MP_E_HIP;
+  if (cur != p->device && hipSetDevice(cur) != hipSuccess && rc == MP_OK) rc = MP_E_HIP;
+  return rc;
 }
 
 int mp_kernel_info_get(const mp_plan* p, int32_t w, int32_t v, mp_kernel_info* out) {

@@ -10,6 +10,10 @@ constexpr int ROW = 16;        // coefficients per max-tree leaf (one DPP row)
 constexpr int ENERGY_PARTS = 32;  // partial sums per signal in the energy kernel
 constexpr int LOG_ROW = 4;
 constexpr int GLEAVES = 256;   // leaves per group when the group preload path is used (FP64)
+// Samples of the static FP64 accumulator used by mp_resynth_static (32 MiB
+// per device), and the devices it tracks.
+constexpr int64_t STATIC_RESYNTH_MAX = (int64_t)1 << 22;
+constexpr int MAX_DEVICES = 64;
 
 // One Gabor system.
 struct DictDev {

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "mpg_internal.h"
@@ -2597,6 +2598,35 @@ hipError_t launch_resynth(const AtomRec* atoms, const SigState* st_, const DictD
   else
     k_resynth<double><<<g, RS_NT, 0, st>>>(atoms, st_, dicts, win64, Lp, acc, (double*)y);
   return hipGetLastError();
+}
+
+// ---- scratch of the allocation-free synthesis (mp_resynth_static) ----
+// The FP64 accumulator of one signal lives in this module-scope array instead
+// of a plan buffer.  Each device that loads the library holds its own copy
+// until the process ends.  In host code the name `scratch` is a host-side
+// stand-in and not a device address: host code uses only the address that
+// hipGetSymbolAddress returns for the current device (kept per device below).
+static __device__ __align__(256) double scratch[STATIC_RESYNTH_MAX];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t static_scratch(double** out, int64_t* n_out) {
+  int dev = -1;
+  CHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    CHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));  // device `dev` is current
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[dev]);
+  *n_out = STATIC_RESYNTH_MAX;
+  return hipSuccess;
 }
 
 hipError_t launch_coefs(const AtomRec* atoms, const SigState* st_, int w, int MR, int64_t n_entries, void* c,

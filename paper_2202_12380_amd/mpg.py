@@ -24,6 +24,7 @@ MP_DFT_F32, MP_DFT_F64 = 0x0, 0x200
 MP_PEDANTIC = 0x100
 MP_SCHED_NT512, MP_SCHED_G128 = 0x1000, 0x2000
 MP_DTYPE_F32, MP_DTYPE_F64 = 0, 1
+MP_STATIC_RESYNTH_MAX = 1 << 22
 MP_STOP_NONE, MP_STOP_K, MP_STOP_SNR, MP_STOP_ENEG, MP_STOP_ZERO = range(5)
 
 
@@ -72,7 +73,7 @@ class mp_stats(C.Structure):
 
 EXPORTS = ["mp_plan_create", "mp_analyze", "mp_run", "mp_run_resets",
            "mp_get_atoms", "mp_get_energy",
-           "mp_get_coefs", "mp_get_residual", "mp_resynth", "mp_signal_info_get",
+           "mp_get_coefs", "mp_get_residual", "mp_resynth", "mp_resynth_static", "mp_signal_info_get",
            "mp_kernel_info_get", "mp_get_kernel", "mp_get_stats", "mp_plan_destroy",
            "mp_autotune", "mp_strerror"]
 
@@ -100,6 +101,7 @@ def lib():
     L.mp_get_coefs.argtypes = [vp, i32, i32, vp, vp]
     L.mp_get_residual.argtypes = [vp, i32, i32, vp, vp]
     L.mp_resynth.argtypes = [vp, i32, vp, i32, vp]
+    L.mp_resynth_static.argtypes = [vp, i32, vp, i32, vp]
     L.mp_signal_info_get.argtypes = [vp, i32, C.POINTER(mp_signal_info)]
     L.mp_kernel_info_get.argtypes = [vp, i32, i32, C.POINTER(mp_kernel_info)]
     L.mp_get_kernel.argtypes = [vp, i32, i32, vp, vp, i64]
@@ -206,6 +208,10 @@ def mp_get_residual(plan: int, sig: int, w: int, dst_ptr: int, stream=None):
 
 def mp_resynth(plan: int, sig: int, y_ptr: int, dtype: int, stream=None):
     _chk(lib().mp_resynth(plan, sig, y_ptr, dtype, _stream(stream)), "mp_resynth")
+
+
+def mp_resynth_static(plan: int, sig: int, y_ptr: int, dtype: int, stream=None):
+    _chk(lib().mp_resynth_static(plan, sig, y_ptr, dtype, _stream(stream)), "mp_resynth_static")
 
 
 def mp_kernel_info_get(plan: int, w: int, v: int) -> mp_kernel_info:

@@ -64,6 +64,7 @@ def test_strerror_and_argument_errors_without_gpu():
     assert L.mp_run(None, 0, 0.0, None) == mpg.MP_E_ARG
     assert L.mp_run_resets(None, None, 0, 0, 0.0, 1, 0.0, None) == mpg.MP_E_ARG
     assert L.mp_resynth(None, 0, None, 0, None) == mpg.MP_E_ARG
+    assert L.mp_resynth_static(None, 0, None, 0, None) == mpg.MP_E_ARG
     # autotuner: bad arguments are rejected before any plan is made
     import ctypes as C
     arr = (mpg.mp_dict * 1)(mpg.mp_dict(0, 64, 16, 64))
