@@ -15,8 +15,10 @@
  *     from the analysis of the true residual (mp_run_resets);
  *   - synthesis of the selected atoms (Sec. 5, Eq. idgtreal).
  * Systems may use Blackman, Hann or Gaussian windows (windows longer than M
- * are folded), and hops that neither nest nor divide M: each pair of systems
- * lives on the common grid gcd(a_w, a_v) x lcm(M_w, M_v) (Sec. 4.2).
+ * are folded), any even M (the analysis of an M that is not a power of two
+ * runs the defining sum of the DFT), and hops that neither nest nor divide M:
+ * each pair of systems lives on the common grid gcd(a_w, a_v) x
+ * lcm(M_w, M_v) (Sec. 4.2).
  *
  * Conventions.
  *   - Every function returns 0 (MP_OK) or a negative MP_E_* code and never
@@ -45,9 +47,11 @@ extern "C" {
 /* ---- return codes ---- */
 #define MP_OK 0
 #define MP_E_ARG (-1)   /* invalid argument (null pointer, bad size, bad index) */
-#define MP_E_GRID (-2)  /* unsupported Gabor system: M not a power of two, gl odd or
-                           gl > 8 M.  Hops need not nest nor divide M: every pair
-                           lives on its common grid (Sec. 2.1, Sec. 4.2)          */
+#define MP_E_GRID (-2)  /* unsupported Gabor system: M odd, gl odd or gl > 8 M, or a
+                           split DFT (MP_DFT_*SPLIT) with M not a power of two.
+                           Neither the hops nor the M need divide each other:
+                           every pair lives on its common grid gcd(a_w, a_v) x
+                           lcm(M_w, M_v) (Sec. 2.1, Sec. 4.2)                      */
 #define MP_E_LEN (-3)   /* a padded length is shorter than gl_v + gl_w of some pair  */
 #define MP_E_NOMEM (-4) /* device or host allocation failed                         */
 #define MP_E_HIP (-5)   /* a HIP runtime call failed                                */

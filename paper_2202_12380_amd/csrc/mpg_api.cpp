@@ -38,7 +38,7 @@ hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs
 hipError_t launch_dgt(bool f64, bool dft64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
                       const void* win, const void* tw, void* planes, void* leaves, const void* gam, int pedantic,
-                      hipStream_t st);
+                      const double2* roots64, hipStream_t st);
 size_t leaf_bytes(bool f64);
 size_t mp_shmem_bytes(bool f64, int nt, int G, int n_groups_max);
 hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st);
@@ -204,15 +204,15 @@ int check_dicts(const mp_dict* d, int W) {
     if (d[w].window != MP_WIN_BLACKMAN && d[w].window != MP_WIN_HANN && d[w].window != MP_WIN_GAUSS)
       return MP_E_ARG;
     if (d[w].gl <= 0 || d[w].a <= 0 || d[w].M <= 0) return MP_E_ARG;
-    if (!is_pow2(d[w].M) || d[w].M < 2) return MP_E_GRID;
+    if (d[w].M < 2 || (d[w].M & 1)) return MP_E_GRID;  // even M: bins 0 .. M/2, Nyquist included
     if ((d[w].gl & 1) || (int64_t)d[w].gl > 8 * (int64_t)d[w].M) return MP_E_GRID;  // longer than M: folded
     // a periodic Blackman or Hann window of length 2 has one nonzero sample:
     // every atom is real, so a pair's d and conj d coincide and the pair
     // adjustment (Eq. dualatprod) divides by 1 - |gamma|^2 = 0
     if (d[w].gl == 2 && d[w].window != MP_WIN_GAUSS && d[w].M >= 4) return MP_E_ARG;
   }
-  // hops need not nest nor divide M: each pair lives on the common grid
-  // gcd(a_w, a_v) x lcm(M_w, M_v) (Sec. 4.2), lcm = max for powers of two
+  // neither the hops nor the numbers of channels need divide each other:
+  // each pair lives on the common grid gcd(a_w, a_v) x lcm(M_w, M_v) (Sec. 4.2)
   return MP_OK;
 }
 
@@ -284,7 +284,7 @@ const char* mp_strerror(int code) {
   switch (code) {
     case MP_OK: return "ok";
     case MP_E_ARG: return "invalid argument";
-    case MP_E_GRID: return "unsupported Gabor system (M not a power of two, gl odd or gl > 8 M)";
+    case MP_E_GRID: return "unsupported Gabor system (M odd, gl odd or gl > 8 M; split DFT with M not a power of two)";
     case MP_E_LEN: return "signal length too short for the kernels (padded L < gl_v + gl_w)";
     case MP_E_NOMEM: return "out of memory";
     case MP_E_HIP: return "HIP runtime error";
@@ -309,6 +309,9 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
   if ((flags & MP_PREC_F64) && (flags & (MP_SCHED_NT512 | MP_SCHED_G128))) return MP_E_ARG;
   int rc = check_dicts(dicts, W);
   if (rc) return rc;
+  // the split DFT is a four-step transform over powers of two
+  for (int w = 0; w < W; ++w)
+    if (dftf && !is_pow2(dicts[w].M)) return MP_E_GRID;
   for (int s = 0; s < batch; ++s)
     if (L[s] <= 0) return MP_E_ARG;
   // the DGT keeps one frame's half-length FFT in LDS
@@ -494,8 +497,10 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
         D.gamma_off = gamoff;
         D.root_off = rootoff;
         magic_u32((uint32_t)D.MR, &D.mr_mul, &D.mr_sh);
+        magic_u32((uint32_t)D.M, &D.m_mul, &D.m_sh);
         D.lpf = (D.MR + ROW - 1) / ROW;
         D.pad = 0;
+        D.pad2[0] = D.pad2[1] = 0;
         twoff += std::max(D.M, 2);  // M/2 twiddles, then their stage-major copy
         gamoff += D.MR;
         rootoff += D.M;
@@ -513,7 +518,8 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       for (int w = 0; w < W; ++w) {
         HCHK(launch_roots(p->hd[w].M, p->hd[w].M / 2, -1, p->d_tw64 + p->hd[w].tw_off,
                           p->d_tw32 + p->hd[w].tw_off, st));
-        HCHK(launch_stage_tw(p->hd[w].M, p->d_tw64 + p->hd[w].tw_off, p->d_tw32 + p->hd[w].tw_off, st));
+        if (is_pow2(p->hd[w].M))  // the radix-2 FFT's stage-major copy
+          HCHK(launch_stage_tw(p->hd[w].M, p->d_tw64 + p->hd[w].tw_off, p->d_tw32 + p->hd[w].tw_off, st));
       }
       // one entry past the end: the FP32 loop reads gamma of two adjacent bins
       ACHK(dalloc(&p->d_gam64, (size_t)gamoff + 1));
@@ -557,7 +563,8 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       int Mmax_all = 0;
       for (int w = 0; w < W; ++w)
         for (int v = 0; v < W; ++v) {
-          const int amin = (int)gcd64(dicts[w].a, dicts[v].a), Mmax = std::max(dicts[w].M, dicts[v].M);
+          const int amin = (int)gcd64(dicts[w].a, dicts[v].a);
+          const int Mmax = (int)(dicts[w].M / gcd64(dicts[w].M, dicts[v].M) * dicts[v].M);  // lcm
           const int half = (dicts[w].gl + dicts[v].gl) / 2;
           const int D = (half + amin - 1) / amin - 1;
           full_max = std::max(full_max, (size_t)(2 * D + 1) * (size_t)Mmax);
@@ -573,7 +580,8 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       for (int w = 0; w < W; ++w)
         for (int v = 0; v < W; ++v) {
           const int idx = w * W + v;
-          const int amin = (int)gcd64(dicts[w].a, dicts[v].a), Mmax = std::max(dicts[w].M, dicts[v].M);
+          const int amin = (int)gcd64(dicts[w].a, dicts[v].a);
+          const int Mmax = (int)(dicts[w].M / gcd64(dicts[w].M, dicts[v].M) * dicts[v].M);  // lcm
           const int half = (dicts[w].gl + dicts[v].gl) / 2;
           const int D = (half + amin - 1) / amin - 1;
           HCHK(launch_roots(Mmax, Mmax, -1, d_roots, nullptr, st));
@@ -660,6 +668,15 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
         if (rows >= ((int64_t)1 << 21)) {
           rc = MP_E_LIMIT;
           goto fail;
+        }
+        // the FP32 loop takes the phase index (ph0 + f phs) mod M_v of frame
+        // f < frames per selection by a 31-bit division
+        for (int w = 0; w < W; ++w) {
+          const PairDev& P = p->hp[w * W + v];
+          if (P.dbox >= 0 && (int64_t)dicts[v].M * ((int64_t)2 * P.dbox / P.sw + 3) >= ((int64_t)1 << 31)) {
+            rc = MP_E_LIMIT;
+            goto fail;
+          }
         }
       }
       ACHK(dalloc(&p->d_tab64, (size_t)tab_total));
@@ -865,7 +882,8 @@ int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream)
     else
       HCHK(launch_dgt(p->f64, dft64, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w], p->batch,
                       p->frames_total[w], (const char*)win + D.win_off * (r64 ? 8 : 4), tw, p->d_planes,
-                      p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
+                      p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0,
+                      p->d_root64 + D.root_off, stream));
   }
   HCHK(hipEventRecord(p->ev[1], stream));
   HCHK(hipEventRecord(p->ev[2], stream));
@@ -890,7 +908,9 @@ static MPArgs mp_args(const mp_plan* p, int64_t max_atoms, double target_snr_db)
   a.gammas = p->f64 ? (const void*)p->d_gam64 : (const void*)p->d_gam32;
   a.roots = p->f64 ? (const void*)p->d_root64 : (const void*)p->d_root32;
   a.n_groups_max = p->n_groups_max;
-  a.pad_ = 0;
+  a.p2 = 1;
+  for (int w = 0; w < p->W; ++w)
+    if (!is_pow2(p->hd[w].M)) a.p2 = 0;
   a.order = p->d_order;
   a.queue = p->d_queue;
   a.W = p->W;
@@ -1008,7 +1028,8 @@ int mp_run_resets(mp_plan* p, const void* x_dev, int32_t dtype, int64_t max_atom
           HCHK(launch_dgt(p->f64, dft64, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR,
                           p->d_fprefix[w], p->batch, p->frames_total[w],
                           (const char*)win + D.win_off * (r64 ? 8 : 4), tw,
-                          p->d_planes, p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
+                          p->d_planes, p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0,
+                          p->d_root64 + D.root_off, stream));
       }
       HCHK(hipStreamSynchronize(stream));
       if (!active) break;

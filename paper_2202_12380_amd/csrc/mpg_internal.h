@@ -15,7 +15,9 @@ constexpr int GLEAVES = 256;   // leaves per group when the group preload path i
 constexpr int64_t STATIC_RESYNTH_MAX = (int64_t)1 << 22;
 constexpr int MAX_DEVICES = 64;
 
-// One Gabor system.
+// One Gabor system.  M is even; it need not be a power of two (then the
+// analysis runs the defining sum of the DFT and the loops take indices mod M
+// by division instead of masks).
 struct DictDev {
   int32_t gl, a, M, MR;        // MR = M/2 + 1 reduced bins
   int64_t win_off;             // offset of its window in the window arrays
@@ -27,6 +29,9 @@ struct DictDev {
   int32_t mr_sh;
   int32_t lpf;                 // max-tree leaves per frame, ceil(MR / ROW)
   int32_t pad;
+  uint32_t m_mul;              // q / M the same way (phase indices mod M when M is not a power of two)
+  int32_t m_sh;
+  int32_t pad2[2];
 };
 
 // Kernel of the ordered pair (target w, source v) on the common grid
@@ -95,7 +100,7 @@ struct MPArgs {
   const int32_t* order;
   int32_t* queue;
   int32_t W, batch, G, logG;
-  int32_t n_groups_max, pad_;
+  int32_t n_groups_max, p2;    // p2: every M of the plan is a power of two
   int64_t K;
   double snr_db;
   uint32_t partner_gate, pedantic;  // pedantic: select by the pair projection energy (Sec. 5)

@@ -464,6 +464,11 @@ __global__ void __launch_bounds__(64) k_energy_fin(const double* __restrict__ pa
 // the bit-reversed scatter and most butterfly strides over the banks at two
 // VALU operations per address (the kernel is bound by VALU issue).  The
 // signal is zero beyond L and circular over L_padded.
+//
+// M not a power of two (logM < 0): the frame is stored in natural order and
+// each bin is the defining sum of the DFT, rho(m) = sum_t u(t) e^{-2 pi i m t
+// / M}, accumulated in FP64 with the phase index m t mod M stepped exactly in
+// integers (roots64 = e^{+2 pi i j / M}, j < M); O(M^2) per frame.
 
 // Frame of workgroup blockIdx.x: the hardware deals workgroups to the 8 XCDs
 // in turn (workgroup i to XCD i mod 8), so XCD x gets one contiguous run of
@@ -486,10 +491,15 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
                                              const int64_t* __restrict__ frame_prefix, int batch,
                                              const R* __restrict__ win, const Cx<R>* __restrict__ tw,
                                              Cx<O>* __restrict__ planes, Leaf<O>* __restrict__ leaves,
-                                             const Cx<O>* __restrict__ gam, int pedantic) {
+                                             const Cx<O>* __restrict__ gam, int pedantic,
+                                             const double2* __restrict__ roots64) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem_raw);
-  const int H = M >> 1, logH = logM - 1;
+  const bool direct = logM < 0;
+  const int H = M >> 1;
+  const int logH = direct ? 0 : logM - 1;  // no FFT stages for the defining sum
+  // first window position >= -gl/2 of the slot at t: t - floor((t + gl/2) / M) M
+  auto first_pos = [&](int t) { return t - (direct ? floor_div32(t + gl / 2, M) : (t + gl / 2) >> logM) * M; };
   const int64_t f = xcd_frame();
   // signal owning global frame f: last s with frame_prefix[s] <= f
   int lo = 0, hi = batch - 1;
@@ -520,7 +530,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
         for (int e = 0; e < 2; ++e) {
           const int i = 2 * (q0 + u * bd) + e;
           const int t = i < H ? i : i - M;
-          const int tt = t - ((t + gl / 2) >> logM) * M;  // first position >= -gl/2
+          const int tt = first_pos(t);
           int l = base + (tt + gl / 2);
           if (l >= Lp) l -= Lp;
           // unconditional loads (stand-in sample 0 and window entry 0 where
@@ -534,7 +544,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
       for (int u = 0; u < 2; ++u) {
         const int q = q0 + u * bd;
         if (q < H) {
-          const int r = logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0;
+          const int r = direct ? q : (logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0);
           buf[dgt_sw(r)] = Cx<R>{v[u][0], v[u][1]};
         }
       }
@@ -549,14 +559,14 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
         // window positions t, t + M, ... in [-gl/2, gl/2) fold onto slot i;
         // the first is t - floor((t + gl/2) / M) M
         R v = (R)0;
-        for (int tt = t - ((t + gl / 2) >> logM) * M; tt < gl / 2; tt += M) {
+        for (int tt = first_pos(t); tt < gl / 2; tt += M) {
           int l = base + (tt + gl / 2);
           if (l >= Lp) l -= Lp;
           if (l < L) v += (R)xs[l] * win[tt + gl / 2];
         }
         v2[e] = v;
       }
-      const int r = logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0;
+      const int r = direct ? q : (logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0);
       buf[dgt_sw(r)] = Cx<R>{v2[0], v2[1]};
     }
   }
@@ -616,7 +626,26 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
     const Cx<R> t = tnext;
     if (m0 + (int)blockDim.x < lpf * ROW) tnext = twid(m + (int)blockDim.x);
     Cx<O> v = {(O)0, (O)0};
-    if (valid) {
+    if (valid && direct) {
+      // u(2q) = buf[q].re, u(2q+1) = buf[q].im; phase indices 2 m q and
+      // m (2q + 1) mod M, both stepped by 2 m mod M
+      const int st2 = (2 * m) % M;
+      int ie = 0, io = m;
+      double sr = 0.0, si = 0.0;
+      for (int q = 0; q < H; ++q) {
+        const Cx<R> z = buf[dgt_sw(q)];
+        const double2 re = roots64[ie], ro = roots64[io];
+        sr += (double)z.re * re.x + (double)z.im * ro.x;
+        si -= (double)z.re * re.y + (double)z.im * ro.y;
+        ie += st2;
+        ie -= ie >= M ? M : 0;
+        io += st2;
+        io -= io >= M ? M : 0;
+      }
+      v.re = (O)sr;
+      v.im = (O)si;
+      out[(uint32_t)m] = v;
+    } else if (valid) {
       const Cx<R> zk = buf[dgt_sw(m & (H - 1))], zr = buf[dgt_sw((H - m) & (H - 1))];
       // even part (zk + conj zr) / 2, odd part (zk - conj zr) / (2i)
       const R er = (R)0.5 * (zk.re + zr.re), ei = (R)0.5 * (zk.im - zr.im);
@@ -1183,8 +1212,9 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
           T.MR = P.MR; T.N = P.N; T.off = P.off; T.lbase = P.lbase;
           T.lpf = P.lpf; T.Mmax = P.Mmax; T.rw = P.rw; T.kr = kk * P.rv;
           T.mulo = P.mulo; T.muhi = P.muhi; T.width = P.width; T.sw = P.sw;
-          T.dbox = P.dbox; T.tab = P.tab; T.pad[0] = (int32_t)dc[lane].gamma_off; T.pad[1] = 0;
-          T.cph = (kk * P.amin) & vmask;
+          T.dbox = P.dbox; T.tab = P.tab; T.pad[0] = (int32_t)dc[lane].gamma_off;
+          T.pad[1] = (P.Mmax & (P.Mmax - 1)) == 0;  // M_max a power of two: indices mod M_max by masks
+          T.cph = (vmask & Dv.M) == 0 ? (kk * P.amin) & vmask : (int)(((int64_t)kk * P.amin) % Dv.M);
           T.nlo = 0; T.nF = 0; T.dlo = 0; T.ilo = 0; T.bpf = 1;
           T.gA_lo = T.gA_n = T.gB_lo = 0;
           if (P.dbox >= 0) {
@@ -1341,8 +1371,18 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
         if (pp[sl]) gg[sl] = gams[T.pad[0] + m];
         const int d = T.dlo + f * T.sw;  // delta = Delta / a_min, in [-dbox, dbox]
         const int mm = T.Mmax - 1;
-        int mu1 = (m * T.rw - T.kr) & mm;
-        if (mu1 > (T.Mmax >> 1)) mu1 -= T.Mmax;
+        // mu = m r_w -/+ k r_v taken mod M_max into (-M_max/2, M_max/2]; the
+        // unreduced values lie in [-M_max/2, M_max + r_w]
+        auto wrapmu = [&](int x) {
+          if (T.pad[1]) {
+            x &= mm;
+          } else {
+            x += x < 0 ? T.Mmax : 0;
+            x -= x >= T.Mmax ? T.Mmax : 0;
+          }
+          return x > (T.Mmax >> 1) ? x - T.Mmax : x;
+        };
+        const int mu1 = wrapmu(m * T.rw - T.kr);
         const int64_t rowoff = T.tab + (int64_t)(d + T.dbox) * T.width - T.mulo;
         bool any = false;
         if (mu1 >= T.mulo && mu1 <= T.muhi) {
@@ -1350,14 +1390,19 @@ __device__ void mp_signal(const MPArgs& A, int s, unsigned char* smem, int lane,
           any = true;
         }
         if (pair) {
-          int mu2 = (m * T.rw + T.kr) & mm;
-          if (mu2 > (T.Mmax >> 1)) mu2 -= T.Mmax;
+          const int mu2 = wrapmu(m * T.rw + T.kr);
           if (mu2 >= T.mulo && mu2 <= T.muhi) {
             h2[sl] = tabs[rowoff + mu2];
             any = true;
           }
         }
-        if (any) ph[sl] = vroots[((d & vmask) * T.cph) & vmask];
+        if (any) {
+          // phase index (k Delta) mod M_v = ((delta mod M_v) cph) mod M_v
+          const int Mv = vmask + 1;
+          const int pi = (Mv & vmask) == 0 ? ((d & vmask) * T.cph) & vmask
+                                           : (int)(((int64_t)mod_pos(d, Mv) * T.cph) % Mv);
+          ph[sl] = vroots[pi];
+        }
         chg[sl] = any;
       }
       if (round == 0) {
@@ -1529,13 +1574,15 @@ __global__ void __launch_bounds__(NT) k_mp(MPArgs A) {
 
 constexpr uint64_t KEY_SENT = ~0ull;     // scratch entry not written
 
-// Row geometry of one target system for the current selection (LDS).  All M
-// are powers of two, so r_w = M_max / M_w is a shift.
+// Row geometry of one target system for the current selection (LDS).  Term t
+// (1: the atom, 2: its conjugate partner) reaches bin m of the target iff
+// d_t = (m - c_t) mod M_w <= span_t; its FP32 kernel entry is then entry d_t
+// of the term's part of the table row (see select_into).
 struct __align__(16) RowT {
   int32_t MR, N, off, lbase;
   int32_t lpf, nlo, nF, ilo;
-  int32_t bpf, item_base, rsh, mm;   // r_w = 1 << rsh, mm = M_max - 1
-  int32_t k1, k2, mspan, hrow0;      // term 1 in the box iff ((m r_w - k1) & mm) <= mspan, term 2 with k2
+  int32_t bpf, item_base, Mw, span1;
+  int32_t c1, c2, span2, hrow0;
   int32_t hstep, slot_base;          // table row of frame f: hrow0 + f hstep; first touched-group slot
   uint32_t ph0, phs;                 // phase index of frame f: (ph0 + f phs) mod M_v
   int32_t gA_lo, gA_n, gB_lo, gB_n;  // touched groups (run A: frames from nlo, run B: wrapped)
@@ -1548,6 +1595,9 @@ struct __align__(16) It32 {
   int32_t p, v, kk, j;
   int32_t pair, T_items, TG, stop;
   int32_t root_off, vmask, partner, pad;
+  int32_t Mv, mv_sh;                 // M_v, and q / M_v == (umulhi(q, mv_mul) + q) >> mv_sh
+  uint32_t mv_mul;
+  int32_t pad2;
   Cx<float> cc;                      // adjusted coefficient c~ of the selected atom (pair)
   double Et;                         // energy decrease of the selection
   int32_t ibase[MAXW];               // first row item of each target
@@ -1576,7 +1626,8 @@ __device__ __forceinline__ C4f ld_c4(const Cx<float>* q) {
 }
 __device__ __forceinline__ void st_c4(Cx<float>* q, const C4f& v) { __builtin_memcpy(q, &v, sizeof(C4f)); }
 
-template <int NT, int SLOTS, int GL>
+// P2: every M of the plan is a power of two (indices mod M by masks).
+template <int NT, int SLOTS, int GL, bool P2>
 __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lane, int wave) {
   if (A.reset_it > 0 && A.state[s].done) return;  // finished in an earlier round of the reset procedure
   constexpr int NW = NT / 64;
@@ -1620,7 +1671,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     c.sw = P.sw; c.sv = P.sv; c.Lpa = 0; c.amin = P.amin;
     c.M = Dw.M;
     c.sw_sh = (P.sw & (P.sw - 1)) ? -1 : (31 - __clz(P.sw));  // -1: a_w / gcd not a power of two
-    c.rw_sh = 31 - __clz(P.rw);
+    c.rw_sh = (P.rw & (P.rw - 1)) ? -1 : (31 - __clz(P.rw));  // -1: M_max / M_w not a power of two
     c.pad = P.cw;          // FP32 table: phase-major rows
     c.width = P.width32;
     c.tab = P.tab_off32;
@@ -1631,8 +1682,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   const bool pow2hops =
       __ballot(lane < W * W && (A.pairs[lane < W * W ? lane : 0].sw & (A.pairs[lane < W * W ? lane : 0].sw - 1)) != 0) == 0ull;
   // dictionary constants, lane u < W holds system u
-  int d_off = 0x7fffffff, d_MR = 1, d_M = 2, d_sh = 0, d_gam = 0, d_root = 0;
-  uint32_t d_mul = 0;
+  int d_off = 0x7fffffff, d_MR = 1, d_M = 2, d_sh = 0, d_gam = 0, d_root = 0, d_msh = 0;
+  uint32_t d_mul = 0, d_mmul = 0;
   if (lane < W) {
     const DictDev D = A.dicts[lane];
     d_off = (int)S.off[lane];
@@ -1642,6 +1693,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     d_mul = D.mr_mul;
     d_gam = (int)D.gamma_off;
     d_root = (int)D.root_off;
+    d_mmul = D.m_mul;
+    d_msh = D.m_sh;
   }
   for (int g = wave; g < ngp; g += NW) {
     uint64_t best = 0ull;
@@ -1714,11 +1767,33 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     RowT T;
     T.MR = P.MR; T.N = P.N; T.off = P.off; T.lbase = P.lbase; T.lpf = P.lpf;
     const int kr = (int)__umul24((uint32_t)kk, (uint32_t)P.rv);
-    T.rsh = P.rw_sh;
-    T.mm = P.Mmax - 1;
-    T.k1 = kr + P.mulo;
-    T.k2 = P.mulo - kr;
-    T.mspan = P.muhi - P.mulo;
+    // Term t's entries (t = 1: the atom, 2: its partner) for bin m of target
+    // u sit at mu' = (m r_w - k_t) mod M_max of the box row (mu' = mu - mu_lo;
+    // k_1 = k r_v + mu_lo, k_2 = mu_lo - k r_v).  With ph_t = (-k_t) mod r_w
+    // and c_t = ((k_t + ph_t) / r_w) mod M_w, mu' = r_w ((m - c_t) mod M_w) +
+    // ph_t (M_max = r_w M_w): the term reaches bin m iff d_t = (m - c_t) mod
+    // M_w <= span_t = floor((mu_hi - mu_lo - ph_t) / r_w), and the phase-major
+    // FP32 row keeps that entry at d_t of phase ph_t's part.
+    const int k1 = kr + P.mulo, k2 = P.mulo - kr, mspan = P.muhi - P.mulo;
+    int ph1, ph2, c1, c2;
+    if (P.rw_sh >= 0) {
+      ph1 = (-k1) & (P.rw - 1);
+      ph2 = (-k2) & (P.rw - 1);
+      c1 = (k1 + ph1) >> P.rw_sh;  // exact multiples of r_w
+      c2 = (k2 + ph2) >> P.rw_sh;
+      T.span1 = (mspan - ph1) >> P.rw_sh;
+      T.span2 = (mspan - ph2) >> P.rw_sh;
+    } else {
+      ph1 = mod_pos(-k1, P.rw);
+      ph2 = mod_pos(-k2, P.rw);
+      c1 = (k1 + ph1) / P.rw;
+      c2 = (k2 + ph2) / P.rw;
+      T.span1 = floor_div32(mspan - ph1, P.rw);
+      T.span2 = floor_div32(mspan - ph2, P.rw);
+    }
+    T.Mw = P.M;
+    T.c1 = P2 ? c1 & (P.M - 1) : mod_pos(c1, P.M);
+    T.c2 = P2 ? c2 & (P.M - 1) : mod_pos(c2, P.M);
     T.pad[0] = d_gam;  // gamma(m) of target u's bins (lane u holds system u's offset)
     const int jsv = (int)__umul24((uint32_t)j, (uint32_t)P.sv);
     int nlo, nhi;
@@ -1731,17 +1806,17 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     }
     const int half = P.M >> 1;
     // bins m in [0, M/2] with m r_w in +-k r_v + [mu_lo, mu_hi] (mod M_max):
-    // the bins [A1, B1] of one term, taken mod M (M a power of two), meet
-    // [0, M/2] in at most two pieces, [A1 mod M, .] and the wrapped [0, .]
+    // the bins [A1, B1] of one term, taken mod M, meet [0, M/2] in at most
+    // two pieces, [A1 mod M, .] and the wrapped [0, .]
     int mlo = 1 << 30, mhi = -1;
     bool t2 = false;  // term 2 (the conjugate partner) reaches a bin of target u
 #pragma unroll
     for (int term = 0; term < 2; ++term) {
       const int base = term == 0 ? kr : -kr;
-      const int A1 = -((-(base + P.mulo)) >> P.rw_sh), B1 = (base + P.muhi) >> P.rw_sh;
+      const int A1 = cdiv_p(base + P.mulo, P.rw, P.rw_sh), B1 = fdiv_p(base + P.muhi, P.rw, P.rw_sh);
       const bool use = term == 0 || pair;
       const bool full = B1 - A1 + 1 >= P.M;
-      const int A1m = A1 & (P.M - 1), B1m = B1 + (A1m - A1);
+      const int A1m = P2 ? A1 & (P.M - 1) : mod_pos(A1, P.M), B1m = B1 + (A1m - A1);
       const int lo0 = full ? 0 : A1m, hi0 = full ? half : min(B1m, half);
       const bool ok0 = use && lo0 <= hi0;
       const bool ok1 = use && !full && B1m >= P.M;  // piece [0, B1m - M]
@@ -1762,16 +1837,22 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     T.bpf = valid ? (mhi >> LOG_ROW) - T.ilo + 1 : 1;
     T.rbpf = __builtin_amdgcn_rcpf((float)T.bpf);  // within 1 ulp of 1 / bpf
     T.pad[1] = __float_as_int(0.5f * T.rbpf);
-    // table rows are phase-major: term t's entries for bins m sit at
-    // phase ((-k_t) mod r_w) of the row, at mu' div r_w
-    const int ph1 = (-T.k1) & (P.rw - 1), ph2 = (-T.k2) & (P.rw - 1);
+    // table rows are phase-major: term t's part starts at ph_t ceil(width / r_w)
     T.hrow0 = (int)P.tab + (int)__umul24((uint32_t)(dlo + P.dbox), (uint32_t)P.width) +
               (int)__umul24((uint32_t)ph1, (uint32_t)P.pad);
     T.pad[2] = __mul24(ph2 - ph1, P.pad);
     T.hstep = (int)__umul24((uint32_t)P.width, (uint32_t)P.sw);
-    const uint32_t cph = __umul24((uint32_t)kk, (uint32_t)P.amin) & (uint32_t)vmask;
-    T.ph0 = (uint32_t)__mul24(dlo, (int)cph);                           // taken mod M_v
-    T.phs = __umul24(cph, (uint32_t)P.sw) & (uint32_t)vmask;          // phases are taken mod M_v
+    // phase index of frame f: (k Delta / a_min ... ) = (ph0 + f phs) mod M_v
+    if (P2) {
+      const uint32_t cph = __umul24((uint32_t)kk, (uint32_t)P.amin) & (uint32_t)vmask;
+      T.ph0 = (uint32_t)__mul24(dlo, (int)cph);                         // taken mod M_v
+      T.phs = __umul24(cph, (uint32_t)P.sw) & (uint32_t)vmask;        // phases are taken mod M_v
+    } else {
+      const int64_t cph = ((int64_t)kk * P.amin) % M_v;
+      const int64_t q = ((int64_t)dlo * cph) % M_v;
+      T.ph0 = (uint32_t)(q < 0 ? q + M_v : q);
+      T.phs = (uint32_t)((cph * P.sw) % M_v);
+    }
     const int t_items = valid ? ((int)__umul24((uint32_t)T.nF, (uint32_t)T.bpf) + 7) & ~7 : 0;  // whole 8-row slots per target
     const int ihi = mhi >> LOG_ROW;
     const int nend = T.nlo + T.nF - 1;
@@ -1794,6 +1875,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     const int T_items = (int)rdlane32((uint32_t)(ib + t_items), W - 1);
     const int TG = (int)rdlane32((uint32_t)(sb + t_groups), W - 1);
     const int root_v = (int)rdlane32((uint32_t)d_root, v);
+    const int msh_v = (int)rdlane32((uint32_t)d_msh, v);
+    const uint32_t mmul_v = rdlane32(d_mmul, v);
     if (lane < W) {
       tgb[lane] = T;
       itb->ibase[lane] = ib;
@@ -1839,6 +1922,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       I[0] = make_int4(p, v, kk, j);
       I[1] = make_int4(pair, T_items, TG, 0);
       I[2] = make_int4(root_v, vmask, partner, (partner && any2) ? 1 : 0);
+      I[3] = make_int4(M_v, msh_v, (int)mmul_v, 0);
       itb->cc = cc;
       itb->Et = Et;
     }
@@ -1846,7 +1930,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
 
   // per-selection values every wave reads from buffer b (one batch of LDS reads)
   struct ItR {
-    int4 I0, I1, I2;
+    int4 I0, I1, I2, I3;
     Cx<float> cc;
     double Et;
     int ibase, sbase, g0, g1;
@@ -1858,6 +1942,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     r.I0 = *reinterpret_cast<const int4*>(&itb->p);
     r.I1 = *reinterpret_cast<const int4*>(&itb->pair);
     r.I2 = *reinterpret_cast<const int4*>(&itb->root_off);
+    r.I3 = P2 ? make_int4(0, 0, 0, 0) : *reinterpret_cast<const int4*>(&itb->Mv);
     r.cc = itb->cc;
     r.Et = itb->Et;
     r.ibase = lane < W ? itb->ibase[lane] : 0x7fffffff;
@@ -1872,8 +1957,14 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   // A slot is 8 rows; 8 lanes per row, each with 2 adjacent bins m0 = 16 i +
   // 2 rl8 and m0 + 1.  fl bit 0: row in grid, 1/2: bin 0/1 valid, 3/4: term 1
   // of bin 0/1 in the box, 5/6: term 2 of bin 0/1, 7: pedantic score.
+  // phase index (ph0 + f phs) mod M_v: a mask when M_v is a power of two,
+  // else a division by M_v (x < 2^31, bounded at plan creation)
+  struct PhaseMod {
+    uint32_t mask, mul;
+    int Mv, sh;
+  };
   auto do_batch = [&](auto has2, uint64_t* o0, uint64_t* o1, const RowT* tg, int qb, int nact, int ibase,
-                      int p, bool pair, uint32_t root_off, uint32_t vmask, Cx<float> cc) {
+                      int p, bool pair, uint32_t root_off, PhaseMod pm, Cx<float> cc) {
     constexpr bool H2 = decltype(has2)::value;  // some bin of this selection sees term 2
     C4f r[SLOTS], gg[SLOTS];
     Cx<float> h1a[SLOTS], h1b[SLOTS], h2a[SLOTS], h2b[SLOTS], ph[SLOTS];
@@ -1909,23 +2000,43 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
         const bool v0 = ok && m0 < T.MR, v1 = ok && m0 + 1 < T.MR;
         const uint32_t e = (uint32_t)T.off + __umul24((uint32_t)n, (uint32_t)T.MR) + (uint32_t)m0;
         const uint32_t hrow = (uint32_t)T.hrow0 + __umul24((uint32_t)f, (uint32_t)T.hstep);
-        const uint32_t mm = (uint32_t)T.mm, step = 1u << T.rsh;
-        const uint32_t u1 = (uint32_t)((m0 << T.rsh) - T.k1) & mm, u1b = (u1 + step) & mm;
-        const uint32_t u2 = (uint32_t)((m0 << T.rsh) - T.k2) & mm, u2b = (u2 + step) & mm;
-        const uint32_t span = (uint32_t)T.mspan;
-        const bool i1a = v0 && u1 <= span, i1b = v1 && u1b <= span;
-        const bool i2a = v0 && pair && u2 <= span, i2b = v1 && pair && u2b <= span;
+        // d_t = (m - c_t) mod M_w for the two bins (valid bins: m <= M_w / 2,
+        // 0 <= c_t < M_w, so one correction suffices)
+        const int Mw = T.Mw;
+        int d1 = m0 - T.c1, d2 = m0 - T.c2;
+        int d1b, d2b;
+        if constexpr (P2) {
+          d1 &= Mw - 1;
+          d2 &= Mw - 1;
+          d1b = (d1 + 1) & (Mw - 1);
+          d2b = (d2 + 1) & (Mw - 1);
+        } else {
+          d1 += d1 < 0 ? Mw : 0;
+          d2 += d2 < 0 ? Mw : 0;
+          d1b = d1 + 1 == Mw ? 0 : d1 + 1;
+          d2b = d2 + 1 == Mw ? 0 : d2 + 1;
+        }
+        const bool i1a = v0 && d1 <= T.span1, i1b = v1 && d1b <= T.span1;
+        const bool i2a = v0 && pair && d2 <= T.span2, i2b = v1 && pair && d2b <= T.span2;
         // every lane loads (out-of-grid lanes from valid stand-in addresses;
         // the second bin of a pair may lie one element past its frame)
         r[sl] = ld_c4(rho + (v0 ? e : (uint32_t)p));
-        h1a[sl] = tabs[i1a ? hrow + (u1 >> T.rsh) : 0u];
-        h1b[sl] = tabs[i1b ? hrow + (u1b >> T.rsh) : 0u];
+        h1a[sl] = tabs[i1a ? hrow + (uint32_t)d1 : 0u];
+        h1b[sl] = tabs[i1b ? hrow + (uint32_t)d1b : 0u];
         if constexpr (H2) {
           const uint32_t hrow2 = hrow + (uint32_t)T.pad[2];
-          h2a[sl] = tabs[i2a ? hrow2 + (u2 >> T.rsh) : 0u];
-          h2b[sl] = tabs[i2b ? hrow2 + (u2b >> T.rsh) : 0u];
+          h2a[sl] = tabs[i2a ? hrow2 + (uint32_t)d2 : 0u];
+          h2b[sl] = tabs[i2b ? hrow2 + (uint32_t)d2b : 0u];
         }
-        ph[sl] = roots[root_off + ((T.ph0 + __umul24((uint32_t)f, T.phs)) & vmask)];
+        {
+          const uint32_t x = T.ph0 + __umul24((uint32_t)f, T.phs);
+          uint32_t pix;
+          if constexpr (P2)
+            pix = x & pm.mask;
+          else
+            pix = x - (uint32_t)magic_div((int)x, pm.mul, pm.sh) * (uint32_t)pm.Mv;
+          ph[sl] = roots[root_off + pix];
+        }
         ee[sl] = e;
         lfi[sl] = (uint32_t)li;
         gg[sl] = C4f{0.0f, 0.0f, 0.0f, 0.0f};
@@ -2040,7 +2151,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     const bool pair = uni_i(cr.I1.x) != 0;
     const int T_items = uni_i(cr.I1.y), TG = uni_i(cr.I1.z);
     const uint32_t root_off = (uint32_t)uni_i(cr.I2.x);
-    const uint32_t vmask = (uint32_t)uni_i(cr.I2.y);
+    const PhaseMod pm{(uint32_t)uni_i(cr.I2.y), (uint32_t)uni_i(cr.I3.z), uni_i(cr.I3.x), uni_i(cr.I3.y)};
     const bool has2 = uni_i(cr.I2.w) != 0;
     const int ibase = cr.ibase, sbase = cr.sbase;
     const Cx<float> cc = cr.cc;
@@ -2106,10 +2217,10 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       if (qb < nslots) {
         do {
           if (has2)
-            do_batch(std::true_type{}, old0, old1, tg, qb, min(bs, nslots - qb), ibase, p, pair, root_off, vmask,
+            do_batch(std::true_type{}, old0, old1, tg, qb, min(bs, nslots - qb), ibase, p, pair, root_off, pm,
                      cc);
           else
-            do_batch(std::false_type{}, old0, old1, tg, qb, min(bs, nslots - qb), ibase, p, pair, root_off, vmask,
+            do_batch(std::false_type{}, old0, old1, tg, qb, min(bs, nslots - qb), ibase, p, pair, root_off, pm,
                      cc);
           qb = grab() * bs;
         } while (qb < nslots);
@@ -2197,7 +2308,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   }
 }
 
-template <int NT, int SLOTS, int GL>
+template <int NT, int SLOTS, int GL, bool P2>
 __global__ void __launch_bounds__(NT) k_mp32(MPArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_next;
@@ -2208,7 +2319,7 @@ __global__ void __launch_bounds__(NT) k_mp32(MPArgs A) {
     const int qi = s_next;
     __syncthreads();
     if (qi >= A.batch) break;
-    mp_signal32<NT, SLOTS, GL>(A, A.order[qi], smem_raw, lane, wave);
+    mp_signal32<NT, SLOTS, GL, P2>(A, A.order[qi], smem_raw, lane, wave);
   }
 }
 
@@ -2443,10 +2554,11 @@ hipError_t launch_energy(const void* x, int dtype, const SigDev* sigs, int batch
 hipError_t launch_dgt(bool f64, bool dft64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
                       const void* win, const void* tw, void* planes, void* leaves, const void* gam, int pedantic,
-                      hipStream_t st) {
+                      const double2* roots64, hipStream_t st) {
   if (frames <= 0) return hipSuccess;
   int logM = 0;
   while ((1 << logM) < M) ++logM;
+  if ((1 << logM) != M) logM = -1;  // defining sum of the DFT
   const bool r64 = f64 || dft64;  // FFT arithmetic in FP64
   const size_t sh = (size_t)(M / 2 + M / 64) * (r64 ? 16 : 8);  // H entries + one pad per 32
   if (sh > 160 * 1024) return hipErrorInvalidValue;
@@ -2461,7 +2573,7 @@ hipError_t launch_dgt(bool f64, bool dft64, const void* x, int dtype, const SigD
                               (int)sh));                                                                    \
     k_dgt<RT, XTT, OT><<<grid, nt, sh, st>>>((const XTT*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,      \
                                              batch, (const RT*)win, (const Cx<RT>*)tw, (Cx<OT>*)planes,     \
-                                             (Leaf<OT>*)leaves, (const Cx<OT>*)gam, pedantic);              \
+                                             (Leaf<OT>*)leaves, (const Cx<OT>*)gam, pedantic, roots64);     \
   } while (0)
   if (f64) {
     if (dtype == 0) MPG_DGT(double, float, double);
@@ -2548,14 +2660,19 @@ static hipError_t launch_mp_t(const MPArgs& a, int grid, bool preload, hipStream
   return hipGetLastError();
 }
 
-template <int NT, int SLOTS, int GL>
+template <int NT, int SLOTS, int GL, bool P2>
 static hipError_t launch_mp32_t(const MPArgs& a, int grid, hipStream_t st) {
   const size_t sh = mp32_lds_bytes<NT, GL>(a.n_groups_max);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  CHK(hipFuncSetAttribute((const void*)k_mp32<NT, SLOTS, GL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  CHK(hipFuncSetAttribute((const void*)k_mp32<NT, SLOTS, GL, P2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)sh));
-  k_mp32<NT, SLOTS, GL><<<grid, NT, sh, st>>>(a);
+  k_mp32<NT, SLOTS, GL, P2><<<grid, NT, sh, st>>>(a);
   return hipGetLastError();
+}
+
+template <int NT, int SLOTS, int GL>
+static hipError_t launch_mp32_p(const MPArgs& a, int grid, hipStream_t st) {
+  return a.p2 ? launch_mp32_t<NT, SLOTS, GL, true>(a, grid, st) : launch_mp32_t<NT, SLOTS, GL, false>(a, grid, st);
 }
 
 // LDS bytes of the MP kernel for the launch shape (0: unsupported shape).
@@ -2579,12 +2696,12 @@ hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st
     return launch_mp_t<double, 512, 4>(a, grid, preload, st);
   }
   if (a.G == 128) {
-    if (nt == 768) return launch_mp32_t<768, 2, 128>(a, grid, st);
-    return launch_mp32_t<512, 2, 128>(a, grid, st);
+    if (nt == 768) return launch_mp32_p<768, 2, 128>(a, grid, st);
+    return launch_mp32_p<512, 2, 128>(a, grid, st);
   }
   if (a.G == 256) {
-    if (nt == 768) return launch_mp32_t<768, 2, 256>(a, grid, st);
-    return launch_mp32_t<512, 2, 256>(a, grid, st);
+    if (nt == 768) return launch_mp32_p<768, 2, 256>(a, grid, st);
+    return launch_mp32_p<512, 2, 256>(a, grid, st);
   }
   return hipErrorInvalidValue;
 }

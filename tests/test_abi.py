@@ -36,7 +36,8 @@ def test_strerror_and_argument_errors_without_gpu():
     assert L.mp_strerror(0) == b"ok"
     assert b"unsupported Gabor system" in L.mp_strerror(mpg.MP_E_GRID)
     cases = [
-        ([(0, 64, 16, 64), (0, 64, 24, 96)], [1024], 1e-4, 0, mpg.MP_E_GRID),   # M not a power of 2
+        ([(0, 64, 16, 64), (0, 64, 24, 95)], [1024], 1e-4, 0, mpg.MP_E_GRID),   # M odd
+        ([(0, 64, 16, 64), (0, 64, 24, 96)], [1024], 1e-4, 0x40, mpg.MP_E_GRID),  # split DFT, M = 96
         ([(0, 1024, 16, 64)], [4096], 1e-4, 0, mpg.MP_E_GRID),                  # gl > 8 M
         ([(3, 64, 16, 64)], [1024], 1e-4, 0, mpg.MP_E_ARG),                     # unknown window
         ([(0, 64, 16, 64)], [64], 1e-4, 0, mpg.MP_E_LEN),                       # too short
