@@ -203,7 +203,8 @@ int mp_autotune(const mp_dict *dicts, int32_t W, const int64_t *L,
  * and the max tree over |rho_0|^2 (Sec. 5.1).  x_dev holds the batch packed
  * back to back in the order given at creation (signal s starts at element
  * sum_{r<s} L[r]); dtype is MP_DTYPE_F32 or MP_DTYPE_F64.  Resets the atom
- * logs. */
+ * logs.  May be captured into a HIP graph (it then enqueues kernels only and
+ * records no timing events for mp_get_stats). */
 int mp_analyze(mp_plan *plan, const void *x_dev, int32_t dtype,
                hipStream_t stream);
 
@@ -211,7 +212,11 @@ int mp_analyze(mp_plan *plan, const void *x_dev, int32_t dtype,
  * max_atoms (<= 0: L_padded/5 per signal), E <= 10^(-target_snr_db/10) E0
  * (target_snr_db <= 0: no SNR rule), E < 0, or max |rho| = 0 (Alg. 1 with
  * the stopping conditions of Sec. 6.1 and Sec. 7).  Continues from the
- * current state when called again without mp_analyze. */
+ * current state when called again without mp_analyze.  Grows the atom logs
+ * when max_atoms exceeds their capacity (the only allocation it makes).  May
+ * be captured into a HIP graph once the logs hold max_atoms (an earlier
+ * mp_run with the same max_atoms); under capture it records no timing
+ * events, and a run that would have to grow the logs returns MP_E_STATE. */
 int mp_run(mp_plan *plan, int64_t max_atoms, double target_snr_db,
            hipStream_t stream);
 

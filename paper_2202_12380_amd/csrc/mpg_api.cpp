@@ -115,6 +115,13 @@ namespace {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// The stream is being captured into a HIP graph: mp_analyze and mp_run then
+// enqueue kernels only (no timing events), and nothing may allocate.
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 int64_t gcd64(int64_t a, int64_t b) {
   while (b) {
     int64_t t = a % b;
@@ -868,9 +875,10 @@ int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream)
   const bool dft64 = !p->f64 && (p->flags & MP_DFT_F64);  // FP64 DFT for an FP32 plan
   const bool r64 = p->f64 || dft64;
   const void* win = r64 ? (const void*)p->d_win64 : (const void*)p->d_win32;
-  HCHK(hipEventRecord(p->ev[0], stream));
+  const bool cap = capturing(stream);
+  if (!cap) HCHK(hipEventRecord(p->ev[0], stream));
   HCHK(launch_energy(x_dev, dtype, p->d_sigs, p->batch, p->d_epart, p->d_state, stream));
-  HCHK(hipEventRecord(p->ev[5], stream));  // the DGT kernels alone: ev[5] -> ev[1]
+  if (!cap) HCHK(hipEventRecord(p->ev[5], stream));  // the DGT kernels alone: ev[5] -> ev[1]
   for (int w = 0; w < p->W; ++w) {
     const DictDev& D = p->hd[w];
     const void* tw = p->dft_fmt >= 0 ? (const void*)(p->d_tw32 + D.tw_off)
@@ -885,8 +893,10 @@ int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream)
                       p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0,
                       p->d_root64 + D.root_off, stream));
   }
-  HCHK(hipEventRecord(p->ev[1], stream));
-  HCHK(hipEventRecord(p->ev[2], stream));
+  if (!cap) {
+    HCHK(hipEventRecord(p->ev[1], stream));
+    HCHK(hipEventRecord(p->ev[2], stream));
+  }
   p->analyzed = true;
   p->ran = false;
   p->last_stream = stream;
@@ -929,12 +939,17 @@ static MPArgs mp_args(const mp_plan* p, int64_t max_atoms, double target_snr_db)
 int mp_run(mp_plan* p, int64_t max_atoms, double target_snr_db, hipStream_t stream) {
   if (!p) return MP_E_ARG;
   if (!p->analyzed) return MP_E_STATE;
+  const bool cap = capturing(stream);
+  if (cap) {  // the atom logs must already hold max_atoms: no allocation under capture
+    for (int s = 0; s < p->batch; ++s)
+      if (p->hs[s].cap < (max_atoms > 0 ? max_atoms : std::max<int64_t>(p->hs[s].Lp / 5, 1))) return MP_E_STATE;
+  }
   int rc = ensure_cap(p, max_atoms, stream);
   if (rc) return rc;
   const MPArgs a = mp_args(p, max_atoms, target_snr_db);
-  HCHK(hipEventRecord(p->ev[3], stream));
+  if (!cap) HCHK(hipEventRecord(p->ev[3], stream));
   HCHK(launch_mp(p->f64, p->nt, a, p->grid, stream));
-  HCHK(hipEventRecord(p->ev[4], stream));
+  if (!cap) HCHK(hipEventRecord(p->ev[4], stream));
   p->last_stream = stream;
   p->last_K = max_atoms;
   p->ran = true;
