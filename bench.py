@@ -108,9 +108,12 @@ def main():
                     help="selections per signal in each autotuner probe (0: default schedule, no autotuning)")
     ap.add_argument("--eps", type=float, action="append", default=None,
                     help="restrict --study noise to these thresholds")
-    ap.add_argument("--workload", choices=["c3", "c5"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c5", "c3m"], default="c3",
                     help="c3 (default): the 256-signal batch of the metric; c5: 16 signals of 2^22 samples in "
-                         "five Blackman systems 128 .. 32768, to 50 dB or 5e5 selections (reported on its own line)")
+                         "five Blackman systems 128 .. 32768, to 50 dB or 5e5 selections (reported on its own line); "
+                         "c3m: the c3 batch in three Blackman systems of M = 3 2^k (192/768/3072, a = M/4), whose "
+                         "loop runs the kernel for numbers of channels that are not powers of two and whose "
+                         "analysis runs the radix-3 DFT (its own line, no CPU baseline)")
     ap.add_argument("--study", choices=["precision", "noise"], default=None,
                     help="precision: analysis DFT in FP16 / BF16 pairs, FP32, FP64 at thresholds "
                          "1e-3 / 1e-4 / 1e-5, agreement with the oracle on sampled signals; "
@@ -139,6 +142,13 @@ def main():
         sys.exit(2)
 
     wl = S.workload(3)
+    p2 = True
+    if args.workload == "c3m":
+        import dataclasses
+        wl = dataclasses.replace(wl, dicts=[(0, g, g // 4, g) for g in (192, 768, 3072)])
+        args.cpu_signals = 0
+        args.fp64_sample = 0
+        p2 = False
     lengths = wl.lengths[: args.batch]
     xs = S.signals(3, batch=args.batch)
     log("generated %d signals, %d samples" % (len(xs), sum(lengths)))
@@ -204,8 +214,8 @@ def main():
     # coefficient with a nonzero kernel entry (16 B) + 8 B per max-tree node written
     alg_bytes = 16.0 * st.updated + 8.0 * (st.blocks + st.l1_groups)
     achieved = alg_bytes / (loop_ms * 1e-3) / 1e9
-    kname = _mp32_name(st)
-    traffic = _traffic(kname)
+    kname = _mp32_name(st, p2)
+    traffic = _traffic(kname, args.workload)
     coefs = sum(int(i.n_coefs) for i in infos)
     dgt_bytes = 4.0 * sum(lengths) * len(wl.dicts) + 8.0 * coefs
     dgt_gbps = dgt_bytes / (st.dgt_ms * 1e-3) / 1e9 if st.dgt_ms > 0 else None
@@ -290,7 +300,8 @@ def main():
 
     loop_rate = atoms / (loop_ms * 1e-3)
     out = {
-        "metric": "MP atoms/sec at 40 dB SNR: batched FP32 vs plain FP64, one MI355X",
+        "metric": ("MP atoms/sec at 40 dB SNR: batched FP32 vs plain FP64, one MI355X" if p2 else
+                   "MP atoms/sec at 40 dB SNR, batched FP32, systems of M = 3 2^k (lcm grids), one MI355X"),
         "value": atoms / (ms_step * 1e-3),
         "unit": "atoms/s",
         "n_gpus": 1,
@@ -304,8 +315,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "batched persistent MP: %d audio-like signals, lengths log-uniform in [2^14, 2^18], "
-                        "3 Blackman systems 256/1024/4096 a=gl/4 M=gl, threshold 1e-4, stop at 40 dB"
-                        % len(lengths),
+                        "3 Blackman systems %s a=gl/4 M=gl, threshold 1e-4, stop at 40 dB"
+                        % (len(lengths), "/".join(str(d[1]) for d in wl.dicts)),
             "batch": len(lengths), "total_samples": int(sum(lengths)), "atoms_per_step": atoms,
             "stop_reasons": {"K": stops[1], "snr": stops[2], "E<0": stops[3], "zero": stops[4]},
             "min_snr_db": float(min(snr_reached)),
@@ -521,9 +532,9 @@ def calib_copy(nbytes):
     print(json.dumps({"calib_copy_bytes": n * 4, "launches": 3}))
 
 
-def _mp32_name(st):
-    """Name of the FP32 loop kernel a plan of powers of two launches."""
-    return "mpg::k_mp32<%d, 2, %d, true>" % (st.threads, st.group_leaves)
+def _mp32_name(st, p2=True):
+    """Name of the FP32 loop kernel a plan launches (p2: every M a power of two)."""
+    return "mpg::k_mp32<%d, 2, %d, %s>" % (st.threads, st.group_leaves, "true" if p2 else "false")
 
 
 def _traffic(kname, workload="c3"):

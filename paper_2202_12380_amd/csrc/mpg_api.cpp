@@ -525,7 +525,8 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       for (int w = 0; w < W; ++w) {
         HCHK(launch_roots(p->hd[w].M, p->hd[w].M / 2, -1, p->d_tw64 + p->hd[w].tw_off,
                           p->d_tw32 + p->hd[w].tw_off, st));
-        if (is_pow2(p->hd[w].M))  // the radix-2 FFT's stage-major copy
+        // the radix-2 stages' twiddle copy (M a power of two, or 3 times one)
+        if (is_pow2(p->hd[w].M) || (p->hd[w].M % 3 == 0 && is_pow2(p->hd[w].M / 3)))
           HCHK(launch_stage_tw(p->hd[w].M, p->d_tw64 + p->hd[w].tw_off, p->d_tw32 + p->hd[w].tw_off, st));
       }
       // one entry past the end: the FP32 loop reads gamma of two adjacent bins

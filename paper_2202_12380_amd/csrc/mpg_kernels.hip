@@ -465,9 +465,14 @@ __global__ void __launch_bounds__(64) k_energy_fin(const double* __restrict__ pa
 // VALU operations per address (the kernel is bound by VALU issue).  The
 // signal is zero beyond L and circular over L_padded.
 //
-// M not a power of two (logM < 0): the frame is stored in natural order and
-// each bin is the defining sum of the DFT, rho(m) = sum_t u(t) e^{-2 pi i m t
-// / M}, accumulated in FP64 with the phase index m t mod M stepped exactly in
+// M = 3 2^k (mode 1): H = 3 P with P a power of two.  The pairs z(3q + r),
+// r = 0, 1, 2, are stored as three bit-reversed sub-arrays of length P and
+// transformed by the same radix-2 stages (no butterfly group crosses a
+// sub-array); the unpacking then combines them, Z(k) = sum_r W_H^{r k}
+// Z_r(k mod P) (decimation in time by 3, W_H = e^{-2 pi i / H}).
+// Other M (mode 2): the frame is stored in natural order and each bin is the
+// defining sum of the DFT, rho(m) = sum_t u(t) e^{-2 pi i m t / M},
+// accumulated in FP64 with the phase index m t mod M stepped exactly in
 // integers (roots64 = e^{+2 pi i j / M}, j < M); O(M^2) per frame.
 
 // Frame of workgroup blockIdx.x: the hardware deals workgroups to the 8 XCDs
@@ -487,7 +492,7 @@ __device__ __forceinline__ int dgt_sw(int i) { return i + (i >> 5); }
 // FP32 plan with the FP64 DFT.
 template <typename R, typename XT, typename O>
 __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const SigDev* __restrict__ sigs,
-                                             int w, int gl, int a, int M, int logM, int MR,
+                                             int w, int gl, int a, int M, int mode, int logP, int MR,
                                              const int64_t* __restrict__ frame_prefix, int batch,
                                              const R* __restrict__ win, const Cx<R>* __restrict__ tw,
                                              Cx<O>* __restrict__ planes, Leaf<O>* __restrict__ leaves,
@@ -495,11 +500,19 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
                                              const double2* __restrict__ roots64) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem_raw);
-  const bool direct = logM < 0;
-  const int H = M >> 1;
-  const int logH = direct ? 0 : logM - 1;  // no FFT stages for the defining sum
+  const bool direct = mode == 2, radix3 = mode == 1;
+  const int H = M >> 1, P = radix3 ? H / 3 : H;
+  const int logH = direct ? 0 : logP;  // radix-2 stages (of each sub-array)
   // first window position >= -gl/2 of the slot at t: t - floor((t + gl/2) / M) M
-  auto first_pos = [&](int t) { return t - (direct ? floor_div32(t + gl / 2, M) : (t + gl / 2) >> logM) * M; };
+  auto first_pos = [&](int t) {
+    return t - (mode == 0 ? (t + gl / 2) >> (logP + 1) : floor_div32(t + gl / 2, M)) * M;
+  };
+  // LDS slot of pair z(q): bit-reversed within its sub-array
+  auto slot_of = [&](int q) -> int {
+    if (direct) return q;
+    const int r = radix3 ? q % 3 : 0, q1 = radix3 ? q / 3 : q;
+    return r * P + (logP > 0 ? (int)(__brev((unsigned)q1) >> (32 - logP)) : 0);
+  };
   const int64_t f = xcd_frame();
   // signal owning global frame f: last s with frame_prefix[s] <= f
   int lo = 0, hi = batch - 1;
@@ -543,10 +556,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int q = q0 + u * bd;
-        if (q < H) {
-          const int r = direct ? q : (logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0);
-          buf[dgt_sw(r)] = Cx<R>{v[u][0], v[u][1]};
-        }
+        if (q < H) buf[dgt_sw(slot_of(q))] = Cx<R>{v[u][0], v[u][1]};
       }
     }
   } else {
@@ -566,8 +576,7 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
         }
         v2[e] = v;
       }
-      const int r = direct ? q : (logH > 0 ? (int)(__brev((unsigned)q) >> (32 - logH)) : 0);
-      buf[dgt_sw(r)] = Cx<R>{v2[0], v2[1]};
+      buf[dgt_sw(slot_of(q))] = Cx<R>{v2[0], v2[1]};
     }
   }
   __syncthreads();
@@ -646,7 +655,32 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
       v.im = (O)si;
       out[(uint32_t)m] = v;
     } else if (valid) {
-      const Cx<R> zk = buf[dgt_sw(m & (H - 1))], zr = buf[dgt_sw((H - m) & (H - 1))];
+      Cx<R> zk, zr;
+      if (radix3) {
+        // Z(k) = Z_0(k mod P) + W^k Z_1(k mod P) + W^{2k} Z_2(k mod P),
+        // W^j = e^{-2 pi i 2 j / M}: tw[j'] for j' < H, -tw[j' - H] above
+        auto twm = [&](int jm) -> Cx<R> {
+          const Cx<R> t0 = tw[(uint32_t)(jm < H ? jm : jm - H)];
+          return jm < H ? t0 : Cx<R>{-t0.re, -t0.im};
+        };
+        auto zcomb = [&](int k) -> Cx<R> {
+          const int kp = k & (P - 1);
+          const Cx<R> a0 = buf[dgt_sw(kp)], a1 = buf[dgt_sw(P + kp)], a2 = buf[dgt_sw(2 * P + kp)];
+          int j1 = 2 * k;
+          j1 -= j1 >= M ? M : 0;
+          int j2 = 2 * j1;
+          j2 -= j2 >= M ? M : 0;
+          const Cx<R> w1 = twm(j1), w2 = twm(j2);
+          return Cx<R>{a0.re + (w1.re * a1.re - w1.im * a1.im) + (w2.re * a2.re - w2.im * a2.im),
+                       a0.im + (w1.re * a1.im + w1.im * a1.re) + (w2.re * a2.im + w2.im * a2.re)};
+        };
+        const int k1 = m < H ? m : m - H, k2 = m == 0 ? 0 : H - m;
+        zk = zcomb(k1);
+        zr = zcomb(k2 < H ? k2 : k2 - H);
+      } else {
+        zk = buf[dgt_sw(m & (H - 1))];
+        zr = buf[dgt_sw((H - m) & (H - 1))];
+      }
       // even part (zk + conj zr) / 2, odd part (zk - conj zr) / (2i)
       const R er = (R)0.5 * (zk.re + zr.re), ei = (R)0.5 * (zk.im - zr.im);
       const R or_ = (R)0.5 * (zk.im + zr.im), oi = (R)0.5 * (zr.re - zk.re);
@@ -2556,9 +2590,17 @@ hipError_t launch_dgt(bool f64, bool dft64, const void* x, int dtype, const SigD
                       const void* win, const void* tw, void* planes, void* leaves, const void* gam, int pedantic,
                       const double2* roots64, hipStream_t st) {
   if (frames <= 0) return hipSuccess;
-  int logM = 0;
-  while ((1 << logM) < M) ++logM;
-  if ((1 << logM) != M) logM = -1;  // defining sum of the DFT
+  // mode 0: M a power of two (H = 2^logP), 1: M = 3 2^k (H = 3 2^logP),
+  // 2: any other M (defining sum)
+  int mode = 2, logP = 0;
+  for (int c = 0; c < 2; ++c) {
+    const int Pc = c == 0 ? M / 2 : M / 6;
+    if (Pc >= 1 && (Pc & (Pc - 1)) == 0 && Pc * (c == 0 ? 2 : 6) == M) {
+      mode = c;
+      while ((1 << logP) < Pc) ++logP;
+      break;
+    }
+  }
   const bool r64 = f64 || dft64;  // FFT arithmetic in FP64
   const size_t sh = (size_t)(M / 2 + M / 64) * (r64 ? 16 : 8);  // H entries + one pad per 32
   if (sh > 160 * 1024) return hipErrorInvalidValue;
@@ -2571,7 +2613,7 @@ hipError_t launch_dgt(bool f64, bool dft64, const void* x, int dtype, const SigD
     if (sh > 64 * 1024)                                                                                     \
       CHK(hipFuncSetAttribute((const void*)k_dgt<RT, XTT, OT>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                               (int)sh));                                                                    \
-    k_dgt<RT, XTT, OT><<<grid, nt, sh, st>>>((const XTT*)x, sigs, w, gl, a, M, logM, MR, frame_prefix,      \
+    k_dgt<RT, XTT, OT><<<grid, nt, sh, st>>>((const XTT*)x, sigs, w, gl, a, M, mode, logP, MR, frame_prefix, \
                                              batch, (const RT*)win, (const Cx<RT>*)tw, (Cx<OT>*)planes,     \
                                              (Leaf<OT>*)leaves, (const Cx<OT>*)gam, pedantic, roots64);     \
   } while (0)
