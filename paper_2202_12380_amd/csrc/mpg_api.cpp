@@ -34,7 +34,7 @@ hipError_t launch_dft_tables(int fmt, int N, int Np, uint16_t* out, hipStream_t 
 hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a, int M,
                            int MR, const int64_t* frame_prefix, int batch, int64_t frames, const float* win,
                            const void* tw, int N1, int N2, const uint16_t* F1, const uint16_t* F2, void* planes,
-                           void* leaves, const void* gam, int pedantic, hipStream_t st);
+                           void* leaves, const void* gam, int pedantic, int64_t max_Lp, hipStream_t st);
 hipError_t launch_dgt(bool f64, bool dft64, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a,
                       int M, int MR, const int64_t* frame_prefix, int batch, int64_t frames,
                       const void* win, const void* tw, void* planes, void* leaves, const void* gam, int pedantic,
@@ -887,7 +887,7 @@ int mp_analyze(mp_plan* p, const void* x_dev, int32_t dtype, hipStream_t stream)
     if (p->dft_fmt >= 0)
       HCHK(launch_dgt_mfma(p->dft_fmt, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w],
                            p->batch, p->frames_total[w], p->d_win32 + D.win_off, tw, p->dft_n1[w],
-                           p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
+                           p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves, (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, p->max_Lp, stream));
     else
       HCHK(launch_dgt(p->f64, dft64, x_dev, dtype, p->d_sigs, w, D.gl, D.a, D.M, D.MR, p->d_fprefix[w], p->batch,
                       p->frames_total[w], (const char*)win + D.win_off * (r64 ? 8 : 4), tw, p->d_planes,
@@ -1039,7 +1039,7 @@ int mp_run_resets(mp_plan* p, const void* x_dev, int32_t dtype, int64_t max_atom
           HCHK(launch_dgt_mfma(p->dft_fmt, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR,
                                p->d_fprefix[w], p->batch, p->frames_total[w], p->d_win32 + D.win_off, tw,
                                p->dft_n1[w], p->dft_n2[w], p->d_dft1[w], p->d_dft2[w], p->d_planes, p->d_leaves,
-                               (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, stream));
+                               (p->f64 ? (const void*)(p->d_gam64 + D.gamma_off) : (const void*)(p->d_gam32 + D.gamma_off)), (p->flags & MP_PEDANTIC) ? 1 : 0, p->max_Lp, stream));
         else
           HCHK(launch_dgt(p->f64, dft64, p->d_res, MP_DTYPE_F64, p->d_sigs_res, w, D.gl, D.a, D.M, D.MR,
                           p->d_fprefix[w], p->batch, p->frames_total[w],

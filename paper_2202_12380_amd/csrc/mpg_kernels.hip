@@ -1005,6 +1005,530 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
 }
 
 // --------------------------------------------------------------------------
+// The same split-precision DGT for H = M/2 = 128 .. 2048, one wave per group
+// of frames, each wave looping over many groups.  A wave stacks FPW = 64 / N1
+// frames into the 64 rows (frame, n1) of the first GEMM; the DFT matrices
+// (split planes re_hi, re_lo, im_hi, im_lo in MFMA operand order) and the
+// twiddles w_H^{n1 k2} of every (n1, k2) tile are staged in LDS once per
+// workgroup.  A 16x16 MFMA result tile (lane: column, four consecutive rows)
+// has the lane layout of a 16x16x16 B operand (lane: column, four
+// consecutive k), so B(n1, k2) passes from the first GEMM to the second in
+// registers, after its twiddle and split.  Z goes through a per-wave LDS
+// buffer for the real-input unpacking, which pairs bins m and H - m.  Waves
+// do not synchronise after the staging.
+
+typedef uint32_t mfw_u2 __attribute__((ext_vector_type(2)));
+typedef float mfw_f2 __attribute__((ext_vector_type(2)));
+
+// (a, b) -> hi: both rounded to the half format (nearest even, packed);
+// lo: the remainders a - hi_a, b - hi_b (exact in FP32), rounded likewise.
+template <int FMT>
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t& hi, uint32_t& lo) {
+  if constexpr (FMT == 0) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 h = __builtin_convertvector(mfw_f2{a, b}, h2);
+    const mfw_f2 hb = __builtin_convertvector(h, mfw_f2);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(mfw_f2{a - hb.x, b - hb.y}, h2));
+  } else {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(mfw_f2{a, b}, b2));
+    const float ha = __uint_as_float(hi << 16), hb = __uint_as_float(hi & 0xFFFF0000u);
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(mfw_f2{a - ha, b - hb}, b2));
+  }
+}
+
+// A complex 16x16x16 operand split into hi and lo halves: four consecutive
+// k (A) or rows (B) per lane, two per 32-bit word.
+struct SplitOp {
+  mf_s4 rh, rl, ih, il;
+};
+__device__ __forceinline__ mf_s4 mfw_pack(uint32_t p0, uint32_t p1) {
+  return __builtin_bit_cast(mf_s4, mfw_u2{p0, p1});
+}
+__device__ __forceinline__ mf_s4 mfw_neg(mf_s4 v) {  // both halves of both words
+  return __builtin_bit_cast(mf_s4, __builtin_bit_cast(mfw_u2, v) ^ mfw_u2{0x80008000u, 0x80008000u});
+}
+template <int FMT>
+__device__ __forceinline__ SplitOp split_op(const float (&re)[4], const float (&im)[4]) {
+  uint32_t h0, l0, h1, l1;
+  SplitOp o;
+  split_pair<FMT>(re[0], re[1], h0, l0);
+  split_pair<FMT>(re[2], re[3], h1, l1);
+  o.rh = mfw_pack(h0, h1);
+  o.rl = mfw_pack(l0, l1);
+  split_pair<FMT>(im[0], im[1], h0, l0);
+  split_pair<FMT>(im[2], im[3], h1, l1);
+  o.ih = mfw_pack(h0, h1);
+  o.il = mfw_pack(l0, l1);
+  return o;
+}
+// Table tile (4 planes, 64 lanes each) from LDS
+__device__ __forceinline__ SplitOp lds_op(const mfw_u2* t, int lane) {
+  SplitOp o;
+  o.rh = __builtin_bit_cast(mf_s4, t[lane]);
+  o.rl = __builtin_bit_cast(mf_s4, t[64 + lane]);
+  o.ih = __builtin_bit_cast(mf_s4, t[128 + lane]);
+  o.il = __builtin_bit_cast(mf_s4, t[192 + lane]);
+  return o;
+}
+// Two consecutive K = 16 operands as one K = 32 operand of the double-rate
+// 16x16x32 MFMA: lane group g holds k-slots 8 g .. 8 g + 7 of A and B alike,
+// here the four k of the first step, then the four of the second, so the
+// product sums the same terms as the two K = 16 products.
+typedef short mf_s8 __attribute__((ext_vector_type(8)));
+struct SplitOp8 {
+  mf_s8 rh, rl, ih, il;
+};
+__device__ __forceinline__ mf_s8 mf_cat(mf_s4 a, mf_s4 b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); }
+__device__ __forceinline__ SplitOp8 mf_cat(const SplitOp& a, const SplitOp& b) {
+  return SplitOp8{mf_cat(a.rh, b.rh), mf_cat(a.rl, b.rl), mf_cat(a.ih, b.ih), mf_cat(a.il, b.il)};
+}
+__device__ __forceinline__ mf_s8 mfw_neg(mf_s8 v) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  return __builtin_bit_cast(mf_s8, __builtin_bit_cast(u4, v) ^ u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u});
+}
+template <int FMT>
+__device__ __forceinline__ mf_f4 mfma32(mf_s8 a, mf_s8 b, mf_f4 c) {
+  if constexpr (FMT == 0) {
+    typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+  } else {
+    typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), c, 0, 0, 0);
+  }
+}
+template <int FMT>
+__device__ __forceinline__ mf_f4 mfma_split(mf_s8 ah, mf_s8 al, mf_s8 bh, mf_s8 bl, mf_f4 c) {
+  c = mfma32<FMT>(ah, bh, c);
+  c = mfma32<FMT>(ah, bl, c);
+  return mfma32<FMT>(al, bh, c);
+}
+// (cr, ci) += A B for split complex operands A = X (data), B = F (table):
+// re = xr fr + xi (-fi), im = xr fi + xi fr
+template <int FMT, typename Op>
+__device__ __forceinline__ void cmac_xf(const Op& X, const Op& F, mf_f4& cr, mf_f4& ci) {
+  const auto nih = mfw_neg(F.ih), nil = mfw_neg(F.il);
+  cr = mfma_split<FMT>(X.rh, X.rl, F.rh, F.rl, cr);
+  cr = mfma_split<FMT>(X.ih, X.il, nih, nil, cr);
+  ci = mfma_split<FMT>(X.rh, X.rl, F.ih, F.il, ci);
+  ci = mfma_split<FMT>(X.ih, X.il, F.rh, F.rl, ci);
+}
+// (cr, ci) += A B for A = F (table), B = data: re = fr br + (-fi) bi, im = fr bi + fi br
+template <int FMT, typename Op>
+__device__ __forceinline__ void cmac_fb(const Op& F, const Op& B, mf_f4& cr, mf_f4& ci) {
+  const auto nih = mfw_neg(F.ih), nil = mfw_neg(F.il);
+  cr = mfma_split<FMT>(F.rh, F.rl, B.rh, B.rl, cr);
+  cr = mfma_split<FMT>(nih, nil, B.ih, B.il, cr);
+  ci = mfma_split<FMT>(F.rh, F.rl, B.ih, B.il, ci);
+  ci = mfma_split<FMT>(F.ih, F.il, B.rh, B.rl, ci);
+}
+// Orders this wave's LDS accesses before and after (a compiler barrier; one
+// wave's LDS operations complete in order).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int LN1, int LN2>
+struct MfwShape {
+  static constexpr int N1 = 1 << LN1, N2 = 1 << LN2, H = N1 * N2, M = 2 * H;
+  static constexpr int T1 = N1 / 16;             // 16-row tiles per frame
+  static constexpr int FPW = 4 / T1;             // frames per wave (64 rows)
+  static constexpr int N2P = N2 < 16 ? 16 : N2;  // K and columns of the first GEMM, padded
+  static constexpr int T2 = N2P / 16;
+  static constexpr int ZP = N2 + 4;              // Z row pitch: 4 mod 8 complex, conflict-free stores
+  static constexpr int ZW = FPW * N1 * ZP;       // Z entries per wave
+  static constexpr int IT = (H + ROW + 63) / 64;  // unpacking passes per frame (H + 1 bins, whole rows)
+  // DFT tiles, step-1 twiddles, Z of the 4 waves, unpacking twiddles, window
+  static constexpr size_t lds_bytes() {
+    return (size_t)(T1 * T1 + T2 * T2) * 4 * 64 * 8 + (size_t)T1 * T2 * 2 * 64 * 16 + (size_t)4 * ZW * 8 +
+           (size_t)H * 8 + (size_t)M * 4;
+  }
+  static_assert(N1 >= 16 && N1 <= 64 && N2 >= 8 && N2 <= N1, "frame-group DGT shape");
+};
+
+// Frame of a frame group: signal, index within the signal, present.
+struct MfwFrame {
+  int s, n;
+  bool ok;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mfw_rsrc(const void* p, uint32_t bytes) {
+  // raw (unstrided) buffer: accesses at or past `bytes` read 0 and write nothing
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int FMT, typename XT, int LN1, int LN2>
+__global__ void __launch_bounds__(256) k_dgt_mfw(const XT* __restrict__ x, const SigDev* __restrict__ sigs, int w,
+                                                 int gl, int a, int MR, const int64_t* __restrict__ frame_prefix,
+                                                 int batch, int64_t frames, const float* __restrict__ win,
+                                                 const Cx<float>* __restrict__ tw, const uint16_t* __restrict__ F1g,
+                                                 const uint16_t* __restrict__ F2g, Cx<float>* __restrict__ planes,
+                                                 Leaf<float>* __restrict__ leaves, const Cx<float>* __restrict__ gam,
+                                                 int pedantic) {
+  using Sh = MfwShape<LN1, LN2>;
+  constexpr int N1 = Sh::N1, N2 = Sh::N2, H = Sh::H, M = Sh::M, T1 = Sh::T1, FPW = Sh::FPW, N2P = Sh::N2P,
+                T2 = Sh::T2, ZP = Sh::ZP;
+  constexpr uint32_t XB = sizeof(XT);
+  constexpr bool PF = XB == 4;  // FP32 samples: the next group's loads fly during this group's GEMMs
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  mfw_u2* sF1 = reinterpret_cast<mfw_u2*>(smem_raw);  // T1 x T1 tiles, 4 planes of 64 lanes
+  mfw_u2* sF2 = sF1 + T1 * T1 * 256;                   // T2 x T2 tiles
+  float4* sTw = reinterpret_cast<float4*>(sF2 + T2 * T2 * 256);  // T1 x T2 tiles, 2 x 64 lanes
+  Cx<float>* sZ = reinterpret_cast<Cx<float>*>(sTw + T1 * T2 * 128);  // 4 waves x ZW
+  Cx<float>* sU = sZ + 4 * Sh::ZW;                                     // e^{-2 pi i m / M}, m < H
+  float* sW = reinterpret_cast<float*>(sU + H);                        // window entries < M (0 past gl)
+  // the wave index as a uniform value, so that everything derived from the
+  // frame group (signal, buffer descriptors) stays in scalar registers
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int c = lane & 15, g = lane >> 4;
+
+  // ---- staging (global tables: plane p at p Np^2 halves, tile t at 256 t) ----
+  {
+    const mfw_u2* g1 = reinterpret_cast<const mfw_u2*>(F1g);
+    const mfw_u2* g2 = reinterpret_cast<const mfw_u2*>(F2g);
+    for (int i = threadIdx.x; i < T1 * T1 * 256; i += 256)
+      sF1[i] = g1[(i >> 6 & 3) * (N1 * N1 / 4) + (i >> 8) * 64 + (i & 63)];
+    for (int i = threadIdx.x; i < T2 * T2 * 256; i += 256)
+      sF2[i] = g2[(i >> 6 & 3) * (N2P * N2P / 4) + (i >> 8) * 64 + (i & 63)];
+    // tile (r, cb), half p: lane l holds w_H^{n1 k2} for n1 = 16 r + 4 (l >> 4)
+    // + 2 p + {0, 1}, k2 = 16 cb + (l & 15) (0 for padding columns)
+    for (int i = threadIdx.x; i < T1 * T2 * 128; i += 256) {
+      const int l = i & 63, p = i >> 6 & 1, t = i >> 7;
+      const int r = t / T2, cb = t - r * T2, k2 = 16 * cb + (l & 15);
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int n1 = 16 * r + 4 * (l >> 4) + 2 * p + u;
+        Cx<float> z = {0.0f, 0.0f};
+        if (k2 < N2) {
+          const int e = 2 * ((n1 * k2) & (H - 1));  // e^{-2 pi i e / M}
+          z = tw[e < H ? e : e - H];
+          if (e >= H) z = Cx<float>{-z.re, -z.im};
+        }
+        v[2 * u] = z.re;
+        v[2 * u + 1] = z.im;
+      }
+      sTw[i] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    for (int i = threadIdx.x; i < H; i += 256) sU[i] = tw[i];
+    for (int i = threadIdx.x; i < M; i += 256) sW[i] = i < gl ? win[i] : 0.0f;
+  }
+  __syncthreads();
+
+  // ---- frame groups: XCD x (workgroups x, x + 8, ...) takes a contiguous
+  // run of groups in proportion to its workgroups; its waves interleave ----
+  const int64_t NG = (frames + FPW - 1) / FPW;
+  const int nb = (int)gridDim.x, xcd = (int)(blockIdx.x & 7);
+  const int nbx = (nb >> 3) + (xcd < (nb & 7) ? 1 : 0);
+  const int before = xcd * (nb >> 3) + (xcd < (nb & 7) ? xcd : (nb & 7));
+  const int64_t grp_hi = NG * (before + nbx) / nb;
+  const int nwx = nbx * 4;
+  int64_t grp = NG * before / nb + (int64_t)(blockIdx.x >> 3) * 4 + wave;
+  Cx<float>* zw = sZ + wave * Sh::ZW;
+  const int lpf = (MR + ROW - 1) >> LOG_ROW;
+  const int KW = (gl + M - 1) / M;  // window entries per slot (more than one: folded window)
+  const __amdgpu_buffer_rsrc_t wrs = mfw_rsrc(win, (uint32_t)gl * 4u);
+
+  // signal of frame f (frames of a wave only increase): last s with
+  // frame_prefix[s] <= f, found once by bisection, then by stepping forward
+  int scur = 0;
+  if (grp < grp_hi) {
+    const int64_t f = grp * FPW;
+    int lo = 0, hi = batch - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (frame_prefix[mid] <= f) lo = mid;
+      else hi = mid - 1;
+    }
+    scur = lo;
+  }
+  auto locate = [&](int64_t gq, MfwFrame (&fi)[FPW]) {
+#pragma unroll
+    for (int fr = 0; fr < FPW; ++fr) {
+      const int64_t f = gq * FPW + fr;
+      fi[fr].ok = f < frames;
+      if (fi[fr].ok)
+        while (scur + 1 < batch && frame_prefix[scur + 1] <= f) ++scur;
+      fi[fr].s = scur;
+      fi[fr].n = fi[fr].ok ? (int)(f - frame_prefix[scur]) : 0;
+    }
+  };
+  // Slot i = 2 (n1 + N1 n2) + e of a frame (A operand row n1 = 16 r + c, k =
+  // n2 = 16 ks + 4 g + j, z(n1 + N1 n2) = u(2q) + i u(2q + 1)) holds window
+  // entries wi + k M < gl, wi = (i + gl/2) mod M, times the samples
+  // (n a - gl/2 + wi + k M) mod Lp.  Range-checked buffer loads read 0 past the
+  // signal's L samples (all of them for an absent frame), so the samples load
+  // without tests; only entries inside the window need the wrap, and they lie
+  // below Lp + Lp/2, so one conditional subtraction suffices.
+  // per-lane parts of the slot and bin indices; passed through an empty asm
+  // at the top of each group so that the compiler recomputes the indices
+  // derived from them instead of keeping dozens of them live across groups
+  int lbase = 2 * (c + N1 * 4 * g) + gl / 2, lnv = lane;
+  auto wslot = [&](int r, int ks, int j, int e) -> uint32_t {
+    return (uint32_t)(lbase + 2 * (16 * r + N1 * (16 * ks + j)) + e) & (uint32_t)(M - 1);
+  };
+  struct Src {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t bb, lpb;
+  };
+  auto source = [&](const MfwFrame& F) -> Src {
+    const SigDev& S = sigs[F.s];
+    const int Lp = (int)S.Lp;
+    int base = F.n * a - gl / 2;
+    if (base < 0) base += Lp;
+    return Src{mfw_rsrc(x + S.x_off, F.ok ? (uint32_t)S.L * XB : 0u), (uint32_t)base * XB, (uint32_t)Lp * XB};
+  };
+  auto sample = [&](const Src& q, uint32_t wi) -> float {
+    uint32_t lb = q.bb + wi * XB;
+    lb = min(lb, lb - q.lpb);
+    if constexpr (XB == 4)
+      return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(q.rs, (int)lb, 0, 0));
+    else
+      return (float)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(q.rs, (int)lb, 0, 0));
+  };
+  auto issue = [&](const MfwFrame (&fi)[FPW], float (&xr)[4][T2][4][2]) {
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const Src q = source(fi[rt / T1]);
+#pragma unroll
+      for (int ks = 0; ks < T2; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) xr[rt][ks][j][e] = sample(q, wslot(rt % T1, ks, j, e));
+    }
+  };
+
+  MfwFrame cur[FPW];
+  float xr[4][T2][4][2];
+  if (grp < grp_hi) {
+    locate(grp, cur);
+    if (PF) issue(cur, xr);
+  }
+  for (; grp < grp_hi; grp += nwx) {
+    asm volatile("" : "+v"(lbase), "+v"(lnv));
+    if (!PF) issue(cur, xr);
+    // ---- window products (first entry from LDS, folded entries from global) ----
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ks = 0; ks < T2; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) xr[rt][ks][j][e] *= sW[wslot(rt % T1, ks, j, e)];
+    if (KW > 1) {
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const Src q = source(cur[rt / T1]);
+#pragma unroll 1
+        for (int k = 1; k < KW; ++k)
+#pragma unroll
+          for (int ks = 0; ks < T2; ++ks)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+              for (int e = 0; e < 2; ++e) {
+                const uint32_t wk = wslot(rt % T1, ks, j, e) + (uint32_t)(k * M);
+                const float wq = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(wrs, (int)(wk * 4u), 0, 0));
+                xr[rt][ks][j][e] += sample(q, wk) * wq;
+              }
+      }
+    }
+    // ---- per-frame power-of-two scale (max |z| * scale in [1/2, 1)), split.
+    // Slots n2 >= N2 (N2 = 8: lanes g >= 2) hold other samples of the frame;
+    // the zero rows n2 >= N2 of the padded F_N2 cancel them, and they are
+    // left out of the maximum. ----
+    float sc[FPW], usc[FPW];
+#pragma unroll
+    for (int fr = 0; fr < FPW; ++fr) {
+      float m_ = 0.0f;
+#pragma unroll
+      for (int r = 0; r < T1; ++r)
+#pragma unroll
+        for (int ks = 0; ks < T2; ++ks)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float v = fmaxf(fabsf(xr[fr * T1 + r][ks][j][0]), fabsf(xr[fr * T1 + r][ks][j][1]));
+            m_ = fmaxf(m_, (N2 >= 16 || 16 * ks + 4 * g + j < N2) ? v : 0.0f);
+          }
+      for (int o = 32; o; o >>= 1) m_ = fmaxf(m_, __shfl_xor(m_, o));
+      int ex = 0;
+      if (m_ > 0.0f) frexpf(m_, &ex);
+      sc[fr] = ldexpf(1.0f, -ex);
+      usc[fr] = ldexpf(1.0f, ex);
+    }
+    SplitOp xa[4][T2];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ks = 0; ks < T2; ++ks) {
+        const float s_ = sc[rt / T1];
+        float re[4], im[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          re[j] = xr[rt][ks][j][0] * s_;
+          im[j] = xr[rt][ks][j][1] * s_;
+        }
+        xa[rt][ks] = split_op<FMT>(re, im);
+      }
+
+    // ---- step 1: B = X F_N2, all 64 rows, columns k2 = 16 cb + c; twiddle
+    // w_H^{n1 k2} and split: lane holds rows n1 = 16 r + 4 g + j of column
+    // k2, the B operand layout of step 2 ----
+    SplitOp bq[T2][4];
+#pragma unroll
+    for (int cb = 0; cb < T2; ++cb) {
+      mf_f4 cr[4], ci[4];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) cr[rt] = ci[rt] = mf_f4{0.0f, 0.0f, 0.0f, 0.0f};
+      if constexpr (T2 % 2 == 0) {  // K = 32 steps: pairs of 16-row blocks of n2
+#pragma unroll
+        for (int ks = 0; ks < T2; ks += 2) {
+          const SplitOp8 F = mf_cat(lds_op(sF2 + (ks * T2 + cb) * 256, lane),
+                                    lds_op(sF2 + ((ks + 1) * T2 + cb) * 256, lane));  // F(n2, k2)
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) cmac_xf<FMT>(mf_cat(xa[rt][ks], xa[rt][ks + 1]), F, cr[rt], ci[rt]);
+        }
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < T2; ++ks) {
+          const SplitOp F = lds_op(sF2 + (ks * T2 + cb) * 256, lane);  // F(n2, k2)
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) cmac_xf<FMT>(xa[rt][ks], F, cr[rt], ci[rt]);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const int r = rt % T1;
+        const float4 w01 = sTw[((r * T2 + cb) * 2) * 64 + lane], w23 = sTw[((r * T2 + cb) * 2 + 1) * 64 + lane];
+        const float tr[4] = {w01.x, w01.z, w23.x, w23.z}, ti[4] = {w01.y, w01.w, w23.y, w23.w};
+        float re[4], im[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          re[j] = cr[rt][j] * tr[j] - ci[rt][j] * ti[j];
+          im[j] = cr[rt][j] * ti[j] + ci[rt][j] * tr[j];
+        }
+        bq[cb][rt] = split_op<FMT>(re, im);
+      }
+    }
+
+    // ---- the next group's samples load during step 2 and the unpacking ----
+    MfwFrame nxt[FPW];
+    if (grp + nwx < grp_hi) {
+      locate(grp + nwx, nxt);
+      if (PF) issue(nxt, xr);
+    }
+
+    // ---- step 2: Z = F_N1 B, one 16-row block k1 = 16 r2 + 4 g + j at a
+    // time; each F_N1 tile serves every frame and column block ----
+#pragma unroll 1
+    for (int r2 = 0; r2 < T1; ++r2) {
+      mf_f4 zr[FPW][T2], zi[FPW][T2];
+#pragma unroll
+      for (int fr = 0; fr < FPW; ++fr)
+#pragma unroll
+        for (int cb = 0; cb < T2; ++cb) zr[fr][cb] = zi[fr][cb] = mf_f4{0.0f, 0.0f, 0.0f, 0.0f};
+      if constexpr (T1 % 2 == 0) {  // K = 32 steps: pairs of 16-row blocks of n1
+#pragma unroll
+        for (int ks2 = 0; ks2 < T1; ks2 += 2) {
+          const SplitOp8 F = mf_cat(lds_op(sF1 + (ks2 * T1 + r2) * 256, lane),
+                                    lds_op(sF1 + ((ks2 + 1) * T1 + r2) * 256, lane));  // F(n1, k1)
+#pragma unroll
+          for (int fr = 0; fr < FPW; ++fr)
+#pragma unroll
+            for (int cb = 0; cb < T2; ++cb)
+              cmac_fb<FMT>(F, mf_cat(bq[cb][fr * T1 + ks2], bq[cb][fr * T1 + ks2 + 1]), zr[fr][cb], zi[fr][cb]);
+        }
+      } else {
+#pragma unroll
+        for (int ks2 = 0; ks2 < T1; ++ks2) {
+          const SplitOp F = lds_op(sF1 + (ks2 * T1 + r2) * 256, lane);  // F(n1, k1) = F(k1, n1)
+#pragma unroll
+          for (int fr = 0; fr < FPW; ++fr)
+#pragma unroll
+            for (int cb = 0; cb < T2; ++cb) cmac_fb<FMT>(F, bq[cb][fr * T1 + ks2], zr[fr][cb], zi[fr][cb]);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < T2; ++cb) {
+        const int k2 = 16 * cb + c;
+        if (N2 >= 16 || k2 < N2) {
+#pragma unroll
+          for (int fr = 0; fr < FPW; ++fr)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              zw[(fr * N1 + 16 * r2 + 4 * g + j) * ZP + k2] =
+                  Cx<float>{zr[fr][cb][j] * usc[fr], zi[fr][cb][j] * usc[fr]};
+        }
+      }
+    }
+    wave_lds_fence();
+
+    // ---- unpack the real-input packing, plane rows, leaves: range-checked
+    // buffer stores drop the lanes past bin H and the non-maximal lanes of a
+    // row, so the passes run without branches.  Without pedantic selection
+    // the passes load nothing from global memory, so they never wait for the
+    // next group's samples. ----
+    auto unpack = [&](auto ped_c) {
+      constexpr bool PED = decltype(ped_c)::value;
+#pragma unroll
+      for (int fr = 0; fr < FPW; ++fr) {
+        if (!cur[fr].ok) continue;  // wave-uniform
+        const SigDev& S = sigs[cur[fr].s];
+        const int64_t n = cur[fr].n;
+        const __amdgpu_buffer_rsrc_t ors = mfw_rsrc(planes + S.coef_base + S.off[w] + n * MR, (uint32_t)MR * 8u);
+        const __amdgpu_buffer_rsrc_t lrs =
+            mfw_rsrc(leaves + S.leaf_base + S.lbase[w] + n * lpf, (uint32_t)lpf * (uint32_t)sizeof(Leaf<float>));
+        const uint32_t p0 = (uint32_t)(S.off[w] + n * MR);
+        const Cx<float>* zf = zw + fr * N1 * ZP;
+        auto zat = [&](int k) { return zf[(k >> LN2) * ZP + (k & (N2 - 1))]; };
+#pragma unroll
+        for (int it = 0; it < Sh::IT; ++it) {
+          const int m = 64 * it + lnv;
+          const bool valid = m <= H;
+          const Cx<float> tu = sU[m & (H - 1)];
+          const Cx<float> t = m == H ? Cx<float>{-1.0f, 0.0f} : tu;
+          const Cx<float> zk = zat(m & (H - 1)), zr_ = zat((H - m) & (H - 1));
+          // even part (zk + conj zr) / 2, odd part (zk - conj zr) / (2i)
+          const float er = 0.5f * (zk.re + zr_.re), ei = 0.5f * (zk.im - zr_.im);
+          const float or_ = 0.5f * (zk.im + zr_.im), oi = 0.5f * (zr_.re - zk.re);
+          Cx<float> v;
+          v.re = er + (t.re * or_ - t.im * oi);
+          v.im = ei + (t.re * oi + t.im * or_);
+          __builtin_amdgcn_raw_buffer_store_b64(mfw_u2{__float_as_uint(v.re), __float_as_uint(v.im)}, ors, m * 8,
+                                                0, 0);
+          float val;
+          if constexpr (PED) {
+            const mfw_u2 gb = __builtin_amdgcn_raw_buffer_load_b64(mfw_rsrc(gam, (uint32_t)MR * 8u), m * 8, 0, 0);
+            val = sel_score<float>(v.re, v.im, Cx<float>{__uint_as_float(gb.x), __uint_as_float(gb.y)},
+                                   m != 0 && m != H);
+          } else {
+            val = v.re * v.re + v.im * v.im;
+          }
+          const uint64_t bits = valid ? val_bits(val) : 0ull;
+          const uint64_t rm = row_max_bits<float>(bits);
+          const uint64_t bal = __ballot(valid && bits == rm);
+          const uint32_t rowbits = (uint32_t)(bal >> (lnv & ~(ROW - 1))) & 0xFFFFu;
+          const bool wr = rowbits && lnv == (lnv & ~(ROW - 1)) + __ffs(rowbits) - 1;
+          const uint64_t key = KeyOps<float>::make(val, p0 + (uint32_t)m);
+          __builtin_amdgcn_raw_buffer_store_b64(mfw_u2{(uint32_t)key, (uint32_t)(key >> 32)}, lrs,
+                                                wr ? (m >> LOG_ROW) * 8 : 0x7FFFFFF8, 0, 0);
+        }
+      }
+    };
+    if (pedantic) unpack(std::true_type{});
+    else unpack(std::false_type{});
+    wave_lds_fence();  // the next group's Z stores follow this group's reads
+#pragma unroll
+    for (int fr = 0; fr < FPW; ++fr) cur[fr] = nxt[fr];
+  }
+}
+
+// --------------------------------------------------------------------------
 // The MP loop (Alg. 1 with Eq. approxResDef, the real-atom pairs of Sec. 5
 // and the residual update of Alg. 3).  One persistent workgroup per signal;
 // signals come from a queue, longest first.
@@ -2640,11 +3164,66 @@ hipError_t launch_dft_tables(int fmt, int N, int Np, uint16_t* out, hipStream_t 
   return hipGetLastError();
 }
 
+template <int FMT, typename XT, int LN1, int LN2>
+static hipError_t launch_dgt_mfw_t(const void* x, const SigDev* sigs, int w, int gl, int a, int MR,
+                                   const int64_t* frame_prefix, int batch, int64_t frames, const float* win,
+                                   const void* tw, const uint16_t* F1, const uint16_t* F2, void* planes,
+                                   void* leaves, const void* gam, int pedantic, hipStream_t st) {
+  using Sh = MfwShape<LN1, LN2>;
+  const auto kern = k_dgt_mfw<FMT, XT, LN1, LN2>;
+  const size_t sh = Sh::lds_bytes();
+  if (sh > 64 * 1024)
+    CHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  // as many workgroups as are resident at once, at most one wave per frame group
+  int dev = 0, ncu = 0, occ = 0;
+  CHK(hipGetDevice(&dev));
+  CHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  CHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, 256, sh));
+  const int64_t groups = (frames + Sh::FPW - 1) / Sh::FPW;
+  const int64_t want = (groups + 3) / 4, cap = (int64_t)(ncu > 0 ? ncu : 1) * (occ > 0 ? occ : 1);
+  const unsigned grid = (unsigned)(want < cap ? want : cap);
+  kern<<<grid, 256, sh, st>>>((const XT*)x, sigs, w, gl, a, MR, frame_prefix, batch, frames, win,
+                              (const Cx<float>*)tw, F1, F2, (Cx<float>*)planes, (Leaf<float>*)leaves,
+                              (const Cx<float>*)gam, pedantic);
+  return hipGetLastError();
+}
+
 hipError_t launch_dgt_mfma(int fmt, const void* x, int dtype, const SigDev* sigs, int w, int gl, int a, int M,
                            int MR, const int64_t* frame_prefix, int batch, int64_t frames, const float* win,
                            const void* tw, int N1, int N2, const uint16_t* F1, const uint16_t* F2, void* planes,
-                           void* leaves, const void* gam, int pedantic, hipStream_t st) {
+                           void* leaves, const void* gam, int pedantic, int64_t max_Lp, hipStream_t st) {
   if (frames <= 0) return hipSuccess;
+  // H = 128 .. 2048: frame groups per wave (the factorisations the plan
+  // makes), while the sample byte offsets of every signal fit in 31 bits
+  const int H = M / 2;
+  if (max_Lp * 8 < ((int64_t)1 << 31) && (H == 128 && N1 == 16 && N2 == 8) || (H == 256 && N1 == 16 && N2 == 16) ||
+      (H == 512 && N1 == 32 && N2 == 16) || (H == 1024 && N1 == 32 && N2 == 32) ||
+      (H == 2048 && N1 == 64 && N2 == 32)) {
+    if (MR != H + 1) return hipErrorInvalidValue;
+#define DGT_MFW(L1, L2)                                                                                        \
+  do {                                                                                                         \
+    if (fmt == 0) {                                                                                            \
+      if (dtype == 0) return launch_dgt_mfw_t<0, float, L1, L2>(x, sigs, w, gl, a, MR, frame_prefix, batch,   \
+                                                                 frames, win, tw, F1, F2, planes, leaves, gam, \
+                                                                 pedantic, st);                               \
+      return launch_dgt_mfw_t<0, double, L1, L2>(x, sigs, w, gl, a, MR, frame_prefix, batch, frames, win, tw,  \
+                                                  F1, F2, planes, leaves, gam, pedantic, st);                  \
+    }                                                                                                          \
+    if (dtype == 0) return launch_dgt_mfw_t<1, float, L1, L2>(x, sigs, w, gl, a, MR, frame_prefix, batch,     \
+                                                               frames, win, tw, F1, F2, planes, leaves, gam,   \
+                                                               pedantic, st);                                 \
+    return launch_dgt_mfw_t<1, double, L1, L2>(x, sigs, w, gl, a, MR, frame_prefix, batch, frames, win, tw, F1, \
+                                                F2, planes, leaves, gam, pedantic, st);                        \
+  } while (0)
+    switch (H) {
+      case 128: DGT_MFW(4, 3);
+      case 256: DGT_MFW(4, 4);
+      case 512: DGT_MFW(5, 4);
+      case 1024: DGT_MFW(5, 5);
+      default: DGT_MFW(6, 5);
+    }
+#undef DGT_MFW
+  }
   const size_t sh = (size_t)M * 8;  // z / B and Z, H complex FP32 each
   if (sh > 160 * 1024) return hipErrorInvalidValue;
   const dim3 grid((unsigned)frames);

@@ -149,6 +149,48 @@ def test_dgt_planes_split_mfma(fmt, tol, dicts, L):
         assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("fmt,tol", [(0x40, 3e-6), (0x80, 5e-5)])
+@pytest.mark.parametrize("pedantic", [False, True])
+def test_dgt_planes_split_mfma_batch(fmt, tol, pedantic):
+    # every frame-group shape of the matrix-core DFT (M = 256 .. 4096, 8 .. 1
+    # frames per wave) on a batch of uneven lengths, so that frame groups
+    # straddle signals, with a folded Gaussian window (gl = 2 M); planes
+    # element by element; without pedantic selection, the first selection has
+    # the largest score of its planes (the leaves hold their 16-bin maxima)
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 256, 64, 256), (0, 512, 128, 512), (2, 2048, 128, 1024), (0, 2048, 512, 2048),
+             (0, 4096, 1024, 4096)]
+    lens = [9000, 4100, 16384, 5000, 8192, 4097]
+    rng = np.random.default_rng(fmt + 5)
+    xs = [rng.standard_normal(L).astype(np.float32).astype(np.float64) for L in lens]
+    flags = fmt | (mpg.MP_PEDANTIC if pedantic else 0)
+    plan = mpg.Plan(dicts, lens, 1e-4, flags)
+    plan.analyze(torch.from_numpy(np.concatenate(xs)).to(torch.float32).cuda())
+    planes = []
+    for s_, (L, v) in enumerate(zip(lens, xs)):
+        Lp = O.padded_length(dicts, L)
+        assert plan.info(s_).L_padded == Lp
+        xp = np.zeros(Lp)
+        xp[:L] = v
+        planes.append([])
+        for w, d in enumerate(dicts):
+            ref = O.dgt(d, xp)
+            got = plan.residual(s_, w).cpu().numpy()
+            assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max(), (s_, w)
+            planes[-1].append(np.abs(got.astype(np.complex128)) ** 2)
+    if not pedantic:
+        # the leaves: the first selection of each signal has the largest
+        # |rho|^2 of its planes (to the rounding of the FP32 score)
+        plan.run(1)
+        for s_ in range(len(lens)):
+            a = plan.atoms(s_)
+            assert len(a) == 1
+            top = max(float(p.max()) for p in planes[s_])
+            sel = planes[s_][int(a["w"][0])][int(a["n"][0]), int(a["m"][0])]
+            assert sel >= top * (1.0 - 1e-6), (s_, sel, top)
+
+
 # --------------------------------------------------------------------------
 # MP loop, FP64: identical atom sequence
 
