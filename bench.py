@@ -89,6 +89,16 @@ def _host_info():
     return {"cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
+def _dft_name(flags):
+    if flags & 0x40:
+        return "FP16 hi/lo pairs on 16x16x32 / 16x16x16 MFMA, FP32 accumulation"
+    if flags & 0x80:
+        return "BF16 hi/lo pairs on 16x16x32 / 16x16x16 MFMA, FP32 accumulation"
+    if flags & 0x200:
+        return "FFT in FP64, coefficients rounded to FP32"
+    return "FFT in FP32"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,9 +111,10 @@ def main():
     ap.add_argument("--fp64-sample", type=int, default=4, help="signals run on the plain FP64 GPU path")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
-    ap.add_argument("--plan-flags", type=lambda v: int(v, 0), default=0,
-                    help="extra plan flags (e.g. 0x100: pedantic selection, 0x20: conjugate partner only "
-                         "when gamma != 0, 0x40 / 0x80: split FP16 / BF16 DFT)")
+    ap.add_argument("--plan-flags", type=lambda v: int(v, 0), default=0x40,
+                    help="plan flags (default 0x40: the analysis DFT in FP16 hi/lo pairs on matrix cores with "
+                         "FP32 accumulation; 0: the FP32 FFT, 0x80: BF16 pairs, 0x100: pedantic selection, "
+                         "0x20: conjugate partner only when gamma != 0)")
     ap.add_argument("--probe-atoms", type=int, default=2000,
                     help="selections per signal in each autotuner probe (0: default schedule, no autotuning)")
     ap.add_argument("--eps", type=float, action="append", default=None,
@@ -321,6 +332,7 @@ def main():
             "stop_reasons": {"K": stops[1], "snr": stops[2], "E<0": stops[3], "zero": stops[4]},
             "min_snr_db": float(min(snr_reached)),
             "plan_flags": args.plan_flags,
+            "analysis_dft": _dft_name(args.plan_flags),
             "schedule": {"threads": int(st.threads), "group_leaves": int(st.group_leaves), "autotune": tune},
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -752,8 +752,10 @@ __device__ __forceinline__ mf_f4 mfma_split(mf_s4 ah, mf_s4 al, mf_s4 bh, mf_s4 
 }
 
 // Operand tile (a, b) of the DFT matrix F(r, c) = w_N^{r c} (zero outside N):
-// lane l holds F(16 a + 4 (l >> 4) + j, 16 b + (l & 15)), j = 0..3; components
-// re_hi, re_lo, im_hi, im_lo, -im_hi, -im_lo, each T*T*256 halves (T = Np/16).
+// lane l holds F(16 a + 4 (l >> 4) + j, 16 b + (l & 15)), j = 0..3; planes
+// re_hi, re_lo, im_hi, im_lo, re_lo 2^11, im_lo 2^11, each T*T*256 halves
+// (T = Np/16).  The last two hold the remainders scaled by 2^11 (MFW_LO_SCALE),
+// which keeps them out of FP16's subnormal range.
 // F is symmetric, so the same tile serves as the B operand of the first GEMM
 // (rows n2, columns k2) and, with (a, b) swapped, as the A operand of the
 // second (rows k1, columns n1).
@@ -778,9 +780,9 @@ __global__ void k_dft_tables(int N, int Np, uint16_t* __restrict__ out) {
   split_half<FMT>((float)im, h, lo);
   out[2 * plane + idx] = h;
   out[3 * plane + idx] = lo;
-  split_half<FMT>((float)-im, h, lo);
-  out[4 * plane + idx] = h;
-  out[5 * plane + idx] = lo;
+  const float fr = (float)re, fi = (float)im;
+  out[4 * plane + idx] = to_half_bits<FMT>((fr - from_half_bits<FMT>(to_half_bits<FMT>(fr))) * 2048.0f);
+  out[5 * plane + idx] = to_half_bits<FMT>((fi - from_half_bits<FMT>(to_half_bits<FMT>(fi))) * 2048.0f);
 }
 
 struct TileOp {
@@ -795,8 +797,9 @@ __device__ __forceinline__ TileOp load_tile(const uint16_t* __restrict__ tab, in
   t.rl = *reinterpret_cast<const mf_s4*>(tab + 1 * plane + idx);
   t.ih = *reinterpret_cast<const mf_s4*>(tab + 2 * plane + idx);
   t.il = *reinterpret_cast<const mf_s4*>(tab + 3 * plane + idx);
-  t.nh = *reinterpret_cast<const mf_s4*>(tab + 4 * plane + idx);
-  t.nl = *reinterpret_cast<const mf_s4*>(tab + 5 * plane + idx);
+  typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+  t.nh = __builtin_bit_cast(mf_s4, __builtin_bit_cast(u2, t.ih) ^ u2{0x80008000u, 0x80008000u});
+  t.nl = __builtin_bit_cast(mf_s4, __builtin_bit_cast(u2, t.il) ^ u2{0x80008000u, 0x80008000u});
   return t;
 }
 
@@ -1020,8 +1023,15 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
 typedef uint32_t mfw_u2 __attribute__((ext_vector_type(2)));
 typedef float mfw_f2 __attribute__((ext_vector_type(2)));
 
+// The lo half of a split operand carries the remainder scaled by 2^11, so
+// that it stays in FP16's normal range (a remainder below 2^-14 would be
+// quantised to 2^-24 absolute, the dominant error of unscaled pairs); the
+// products with a lo factor are summed apart and scaled back by 2^-11.
+constexpr float MFW_LO_SCALE = 2048.0f, MFW_LO_UNSCALE = 1.0f / 2048.0f;
+
 // (a, b) -> hi: both rounded to the half format (nearest even, packed);
-// lo: the remainders a - hi_a, b - hi_b (exact in FP32), rounded likewise.
+// lo: the remainders a - hi_a, b - hi_b (exact in FP32) times 2^11, rounded
+// likewise.
 template <int FMT>
 __device__ __forceinline__ void split_pair(float a, float b, uint32_t& hi, uint32_t& lo) {
   if constexpr (FMT == 0) {
@@ -1029,12 +1039,14 @@ __device__ __forceinline__ void split_pair(float a, float b, uint32_t& hi, uint3
     const h2 h = __builtin_convertvector(mfw_f2{a, b}, h2);
     const mfw_f2 hb = __builtin_convertvector(h, mfw_f2);
     hi = __builtin_bit_cast(uint32_t, h);
-    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(mfw_f2{a - hb.x, b - hb.y}, h2));
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(
+                                          mfw_f2{(a - hb.x) * MFW_LO_SCALE, (b - hb.y) * MFW_LO_SCALE}, h2));
   } else {
     typedef __bf16 b2 __attribute__((ext_vector_type(2)));
     hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(mfw_f2{a, b}, b2));
     const float ha = __uint_as_float(hi << 16), hb = __uint_as_float(hi & 0xFFFF0000u);
-    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(mfw_f2{a - ha, b - hb}, b2));
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(
+                                          mfw_f2{(a - ha) * MFW_LO_SCALE, (b - hb) * MFW_LO_SCALE}, b2));
   }
 }
 
@@ -1098,30 +1110,38 @@ __device__ __forceinline__ mf_f4 mfma32(mf_s8 a, mf_s8 b, mf_f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), c, 0, 0, 0);
   }
 }
-template <int FMT>
-__device__ __forceinline__ mf_f4 mfma_split(mf_s8 ah, mf_s8 al, mf_s8 bh, mf_s8 bl, mf_f4 c) {
-  c = mfma32<FMT>(ah, bh, c);
-  c = mfma32<FMT>(ah, bl, c);
-  return mfma32<FMT>(al, bh, c);
+// Accumulators of one complex output tile: hi*hi products, and products
+// with one lo factor (scaled by 2^11); value = h + 2^-11 l.
+struct CAcc {
+  mf_f4 rh, rl, ih, il;
+};
+__device__ __forceinline__ void cacc_zero(CAcc& a) {
+  a.rh = a.rl = a.ih = a.il = mf_f4{0.0f, 0.0f, 0.0f, 0.0f};
 }
-// (cr, ci) += A B for split complex operands A = X (data), B = F (table):
-// re = xr fr + xi (-fi), im = xr fi + xi fr
-template <int FMT, typename Op>
-__device__ __forceinline__ void cmac_xf(const Op& X, const Op& F, mf_f4& cr, mf_f4& ci) {
-  const auto nih = mfw_neg(F.ih), nil = mfw_neg(F.il);
-  cr = mfma_split<FMT>(X.rh, X.rl, F.rh, F.rl, cr);
-  cr = mfma_split<FMT>(X.ih, X.il, nih, nil, cr);
-  ci = mfma_split<FMT>(X.rh, X.rl, F.ih, F.il, ci);
-  ci = mfma_split<FMT>(X.ih, X.il, F.rh, F.rl, ci);
+__device__ __forceinline__ float cacc_re(const CAcc& a, int j) { return fmaf(a.rl[j], MFW_LO_UNSCALE, a.rh[j]); }
+__device__ __forceinline__ float cacc_im(const CAcc& a, int j) { return fmaf(a.il[j], MFW_LO_UNSCALE, a.ih[j]); }
+template <int FMT, typename V>
+__device__ __forceinline__ mf_f4 mfw_mma(V a, V b, mf_f4 c) {
+  if constexpr (sizeof(V) == 16) return mfma32<FMT>(a, b, c);
+  else return mfma16<FMT>(a, b, c);
 }
-// (cr, ci) += A B for A = F (table), B = data: re = fr br + (-fi) bi, im = fr bi + fi br
+// (a + i b)(c + i d) for split complex operands P (A side) and Q (B side),
+// re = ac - bd, im = ad + bc, each real product hi hi + (hi lo + lo hi)
 template <int FMT, typename Op>
-__device__ __forceinline__ void cmac_fb(const Op& F, const Op& B, mf_f4& cr, mf_f4& ci) {
-  const auto nih = mfw_neg(F.ih), nil = mfw_neg(F.il);
-  cr = mfma_split<FMT>(F.rh, F.rl, B.rh, B.rl, cr);
-  cr = mfma_split<FMT>(nih, nil, B.ih, B.il, cr);
-  ci = mfma_split<FMT>(F.rh, F.rl, B.ih, B.il, ci);
-  ci = mfma_split<FMT>(F.ih, F.il, B.rh, B.rl, ci);
+__device__ __forceinline__ void cmac(const Op& P, const Op& Q, CAcc& a) {
+  const auto qnh = mfw_neg(Q.ih), qnl = mfw_neg(Q.il);
+  a.rh = mfw_mma<FMT>(P.rh, Q.rh, a.rh);
+  a.rh = mfw_mma<FMT>(P.ih, qnh, a.rh);
+  a.rl = mfw_mma<FMT>(P.rh, Q.rl, a.rl);
+  a.rl = mfw_mma<FMT>(P.rl, Q.rh, a.rl);
+  a.rl = mfw_mma<FMT>(P.ih, qnl, a.rl);
+  a.rl = mfw_mma<FMT>(P.il, qnh, a.rl);
+  a.ih = mfw_mma<FMT>(P.rh, Q.ih, a.ih);
+  a.ih = mfw_mma<FMT>(P.ih, Q.rh, a.ih);
+  a.il = mfw_mma<FMT>(P.rh, Q.il, a.il);
+  a.il = mfw_mma<FMT>(P.rl, Q.ih, a.il);
+  a.il = mfw_mma<FMT>(P.ih, Q.rl, a.il);
+  a.il = mfw_mma<FMT>(P.il, Q.rh, a.il);
 }
 // Orders this wave's LDS accesses before and after (a compiler barrier; one
 // wave's LDS operations complete in order).
@@ -1146,6 +1166,9 @@ struct MfwShape {
     return (size_t)(T1 * T1 + T2 * T2) * 4 * 64 * 8 + (size_t)T1 * T2 * 2 * 64 * 16 + (size_t)4 * ZW * 8 +
            (size_t)H * 8 + (size_t)M * 4;
   }
+  // waves per SIMD that the LDS admits (four 256-thread workgroups at most),
+  // asked of the register allocator
+  static constexpr int WPE = lds_bytes() <= 40 * 1024 ? 4 : (lds_bytes() <= 53 * 1024 ? 3 : (lds_bytes() <= 80 * 1024 ? 2 : 1));
   static_assert(N1 >= 16 && N1 <= 64 && N2 >= 8 && N2 <= N1, "frame-group DGT shape");
 };
 
@@ -1161,7 +1184,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t mfw_rsrc(const void* p, uint32
 }
 
 template <int FMT, typename XT, int LN1, int LN2>
-__global__ void __launch_bounds__(256) k_dgt_mfw(const XT* __restrict__ x, const SigDev* __restrict__ sigs, int w,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MfwShape<LN1, LN2>::WPE)))
+k_dgt_mfw(const XT* __restrict__ x, const SigDev* __restrict__ sigs, int w,
                                                  int gl, int a, int MR, const int64_t* __restrict__ frame_prefix,
                                                  int batch, int64_t frames, const float* __restrict__ win,
                                                  const Cx<float>* __restrict__ tw, const uint16_t* __restrict__ F1g,
@@ -1189,10 +1213,12 @@ __global__ void __launch_bounds__(256) k_dgt_mfw(const XT* __restrict__ x, const
   {
     const mfw_u2* g1 = reinterpret_cast<const mfw_u2*>(F1g);
     const mfw_u2* g2 = reinterpret_cast<const mfw_u2*>(F2g);
+    // LDS planes re_hi, re_lo 2^11, im_hi, im_lo 2^11 = global planes 0, 4, 2, 5
+    auto gplane = [](int p) { return (p & 1) ? 4 + (p >> 1) : p; };
     for (int i = threadIdx.x; i < T1 * T1 * 256; i += 256)
-      sF1[i] = g1[(i >> 6 & 3) * (N1 * N1 / 4) + (i >> 8) * 64 + (i & 63)];
+      sF1[i] = g1[gplane(i >> 6 & 3) * (N1 * N1 / 4) + (i >> 8) * 64 + (i & 63)];
     for (int i = threadIdx.x; i < T2 * T2 * 256; i += 256)
-      sF2[i] = g2[(i >> 6 & 3) * (N2P * N2P / 4) + (i >> 8) * 64 + (i & 63)];
+      sF2[i] = g2[gplane(i >> 6 & 3) * (N2P * N2P / 4) + (i >> 8) * 64 + (i & 63)];
     // tile (r, cb), half p: lane l holds w_H^{n1 k2} for n1 = 16 r + 4 (l >> 4)
     // + 2 p + {0, 1}, k2 = 16 cb + (l & 15) (0 for padding columns)
     for (int i = threadIdx.x; i < T1 * T2 * 128; i += 256) {
@@ -1381,40 +1407,35 @@ __global__ void __launch_bounds__(256) k_dgt_mfw(const XT* __restrict__ x, const
     // k2, the B operand layout of step 2 ----
     SplitOp bq[T2][4];
 #pragma unroll
-    for (int cb = 0; cb < T2; ++cb) {
-      mf_f4 cr[4], ci[4];
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) cr[rt] = ci[rt] = mf_f4{0.0f, 0.0f, 0.0f, 0.0f};
-      if constexpr (T2 % 2 == 0) {  // K = 32 steps: pairs of 16-row blocks of n2
-#pragma unroll
-        for (int ks = 0; ks < T2; ks += 2) {
-          const SplitOp8 F = mf_cat(lds_op(sF2 + (ks * T2 + cb) * 256, lane),
-                                    lds_op(sF2 + ((ks + 1) * T2 + cb) * 256, lane));  // F(n2, k2)
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt) cmac_xf<FMT>(mf_cat(xa[rt][ks], xa[rt][ks + 1]), F, cr[rt], ci[rt]);
-        }
-      } else {
-#pragma unroll
-        for (int ks = 0; ks < T2; ++ks) {
-          const SplitOp F = lds_op(sF2 + (ks * T2 + cb) * 256, lane);  // F(n2, k2)
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt) cmac_xf<FMT>(xa[rt][ks], F, cr[rt], ci[rt]);
-        }
-      }
+    for (int cb = 0; cb < T2; ++cb)
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) {
+        // one output tile at a time (its accumulators alone live); the table
+        // tiles are LDS reads, repeated per row block
+        CAcc acc;
+        cacc_zero(acc);
+        if constexpr (T2 % 2 == 0) {  // K = 32 steps: pairs of 16-row blocks of n2
+#pragma unroll
+          for (int ks = 0; ks < T2; ks += 2)
+            cmac<FMT>(mf_cat(xa[rt][ks], xa[rt][ks + 1]),
+                      mf_cat(lds_op(sF2 + (ks * T2 + cb) * 256, lane), lds_op(sF2 + ((ks + 1) * T2 + cb) * 256, lane)),
+                      acc);  // F(n2, k2)
+        } else {
+#pragma unroll
+          for (int ks = 0; ks < T2; ++ks) cmac<FMT>(xa[rt][ks], lds_op(sF2 + (ks * T2 + cb) * 256, lane), acc);
+        }
         const int r = rt % T1;
         const float4 w01 = sTw[((r * T2 + cb) * 2) * 64 + lane], w23 = sTw[((r * T2 + cb) * 2 + 1) * 64 + lane];
         const float tr[4] = {w01.x, w01.z, w23.x, w23.z}, ti[4] = {w01.y, w01.w, w23.y, w23.w};
         float re[4], im[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          re[j] = cr[rt][j] * tr[j] - ci[rt][j] * ti[j];
-          im[j] = cr[rt][j] * ti[j] + ci[rt][j] * tr[j];
+          const float cr = cacc_re(acc, j), ci = cacc_im(acc, j);
+          re[j] = cr * tr[j] - ci * ti[j];
+          im[j] = cr * ti[j] + ci * tr[j];
         }
         bq[cb][rt] = split_op<FMT>(re, im);
       }
-    }
 
     // ---- the next group's samples load during step 2 and the unpacking ----
     MfwFrame nxt[FPW];
@@ -1423,49 +1444,43 @@ __global__ void __launch_bounds__(256) k_dgt_mfw(const XT* __restrict__ x, const
       if (PF) issue(nxt, xr);
     }
 
-    // ---- step 2: Z = F_N1 B, one 16-row block k1 = 16 r2 + 4 g + j at a
-    // time; each F_N1 tile serves every frame and column block ----
+    // ---- step 2: Z = F_N1 B, one 16-row block k1 = 16 r2 + 4 g + j and one
+    // frame at a time ----
 #pragma unroll 1
-    for (int r2 = 0; r2 < T1; ++r2) {
-      mf_f4 zr[FPW][T2], zi[FPW][T2];
+    for (int r2 = 0; r2 < T1; ++r2)
 #pragma unroll
-      for (int fr = 0; fr < FPW; ++fr)
+      for (int fr = 0; fr < FPW; ++fr) {
+        CAcc za[T2];
 #pragma unroll
-        for (int cb = 0; cb < T2; ++cb) zr[fr][cb] = zi[fr][cb] = mf_f4{0.0f, 0.0f, 0.0f, 0.0f};
-      if constexpr (T1 % 2 == 0) {  // K = 32 steps: pairs of 16-row blocks of n1
+        for (int cb = 0; cb < T2; ++cb) cacc_zero(za[cb]);
+        if constexpr (T1 % 2 == 0) {  // K = 32 steps: pairs of 16-row blocks of n1
 #pragma unroll
-        for (int ks2 = 0; ks2 < T1; ks2 += 2) {
-          const SplitOp8 F = mf_cat(lds_op(sF1 + (ks2 * T1 + r2) * 256, lane),
-                                    lds_op(sF1 + ((ks2 + 1) * T1 + r2) * 256, lane));  // F(n1, k1)
-#pragma unroll
-          for (int fr = 0; fr < FPW; ++fr)
+          for (int ks2 = 0; ks2 < T1; ks2 += 2) {
+            const SplitOp8 F = mf_cat(lds_op(sF1 + (ks2 * T1 + r2) * 256, lane),
+                                      lds_op(sF1 + ((ks2 + 1) * T1 + r2) * 256, lane));  // F(n1, k1)
 #pragma unroll
             for (int cb = 0; cb < T2; ++cb)
-              cmac_fb<FMT>(F, mf_cat(bq[cb][fr * T1 + ks2], bq[cb][fr * T1 + ks2 + 1]), zr[fr][cb], zi[fr][cb]);
+              cmac<FMT>(F, mf_cat(bq[cb][fr * T1 + ks2], bq[cb][fr * T1 + ks2 + 1]), za[cb]);
+          }
+        } else {
+#pragma unroll
+          for (int ks2 = 0; ks2 < T1; ++ks2) {
+            const SplitOp F = lds_op(sF1 + (ks2 * T1 + r2) * 256, lane);  // F(n1, k1) = F(k1, n1)
+#pragma unroll
+            for (int cb = 0; cb < T2; ++cb) cmac<FMT>(F, bq[cb][fr * T1 + ks2], za[cb]);
+          }
         }
-      } else {
 #pragma unroll
-        for (int ks2 = 0; ks2 < T1; ++ks2) {
-          const SplitOp F = lds_op(sF1 + (ks2 * T1 + r2) * 256, lane);  // F(n1, k1) = F(k1, n1)
-#pragma unroll
-          for (int fr = 0; fr < FPW; ++fr)
-#pragma unroll
-            for (int cb = 0; cb < T2; ++cb) cmac_fb<FMT>(F, bq[cb][fr * T1 + ks2], zr[fr][cb], zi[fr][cb]);
-        }
-      }
-#pragma unroll
-      for (int cb = 0; cb < T2; ++cb) {
-        const int k2 = 16 * cb + c;
-        if (N2 >= 16 || k2 < N2) {
-#pragma unroll
-          for (int fr = 0; fr < FPW; ++fr)
+        for (int cb = 0; cb < T2; ++cb) {
+          const int k2 = 16 * cb + c;
+          if (N2 >= 16 || k2 < N2) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
               zw[(fr * N1 + 16 * r2 + 4 * g + j) * ZP + k2] =
-                  Cx<float>{zr[fr][cb][j] * usc[fr], zi[fr][cb][j] * usc[fr]};
+                  Cx<float>{cacc_re(za[cb], j) * usc[fr], cacc_im(za[cb], j) * usc[fr]};
+          }
         }
       }
-    }
     wave_lds_fence();
 
     // ---- unpack the real-input packing, plane rows, leaves: range-checked
@@ -1485,13 +1500,16 @@ __global__ void __launch_bounds__(256) k_dgt_mfw(const XT* __restrict__ x, const
             mfw_rsrc(leaves + S.leaf_base + S.lbase[w] + n * lpf, (uint32_t)lpf * (uint32_t)sizeof(Leaf<float>));
         const uint32_t p0 = (uint32_t)(S.off[w] + n * MR);
         const Cx<float>* zf = zw + fr * N1 * ZP;
-        auto zat = [&](int k) { return zf[(k >> LN2) * ZP + (k & (N2 - 1))]; };
+        auto zat = [&](int k) { return zf[k + 4 * (k >> LN2)]; };  // row pitch ZP = N2 + 4
 #pragma unroll
         for (int it = 0; it < Sh::IT; ++it) {
           const int m = 64 * it + lnv;
           const bool valid = m <= H;
+          // e^{-2 pi i m / M}; bin H takes -1 = -e^0 (a sign, not a branch, so
+          // that the passes form one block the scheduler can interleave)
           const Cx<float> tu = sU[m & (H - 1)];
-          const Cx<float> t = m == H ? Cx<float>{-1.0f, 0.0f} : tu;
+          const float sg = m == H ? -1.0f : 1.0f;
+          const Cx<float> t = {tu.re * sg, tu.im * sg};
           const Cx<float> zk = zat(m & (H - 1)), zr_ = zat((H - m) & (H - 1));
           // even part (zk + conj zr) / 2, odd part (zk - conj zr) / (2i)
           const float er = 0.5f * (zk.re + zr_.re), ei = 0.5f * (zk.im - zr_.im);

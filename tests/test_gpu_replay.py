@@ -25,7 +25,9 @@ def _torch():
     return torch
 
 
-def test_fp32_c3_sampled_signals_whole_run():
+@pytest.mark.parametrize("flags", [0x40, 0x0])
+def test_fp32_c3_sampled_signals_whole_run(flags):
+    # analysis in FP16 pairs on matrix cores (0x40, as benchmarked) or the FP32 FFT
     _torch()
     wl = S.workload(3)
     xs = S.signals(3)
@@ -33,7 +35,7 @@ def test_fp32_c3_sampled_signals_whole_run():
     pick = [int(order[0]), int(order[1]), int(order[len(xs) // 2]), int(order[-1])]
     sub = [xs[i].astype(np.float32) for i in pick]
     plan, ga, cps = gpu_run_staged(wl.dicts, sub, wl.eps, [1000, 6000, 1 << 17], snr_db=40.0,
-                                   keep=range(len(sub)))
+                                   keep=range(len(sub)), flags=flags)
     for j, i in enumerate(pick):
         x = sub[j].astype(np.float64)
         orc = oracle_run(wl.dicts, x, wl.eps, K=1 << 17, snr_db=40.0)
