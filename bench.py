@@ -111,10 +111,12 @@ def main():
     ap.add_argument("--fp64-sample", type=int, default=4, help="signals run on the plain FP64 GPU path")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
-    ap.add_argument("--plan-flags", type=lambda v: int(v, 0), default=0x40,
-                    help="plan flags (default 0x40: the analysis DFT in FP16 hi/lo pairs on matrix cores with "
-                         "FP32 accumulation; 0: the FP32 FFT, 0x80: BF16 pairs, 0x100: pedantic selection, "
-                         "0x20: conjugate partner only when gamma != 0)")
+    ap.add_argument("--plan-flags", type=lambda v: int(v, 0), default=None,
+                    help="plan flags (default for c3: 0x40, the analysis DFT in FP16 hi/lo pairs on matrix cores "
+                         "with FP32 accumulation; for c5, c3m and the studies: 0, the FP32 FFT, since the split "
+                         "DFT takes powers of two up to 16384 bins; 0x80: BF16 pairs, 0x100: pedantic selection, "
+                         "0x20: conjugate partner only when gamma != 0, 0x1000/0x2000/0x4000/0x8000: a fixed "
+                         "schedule instead of the autotuner's)")
     ap.add_argument("--probe-atoms", type=int, default=2000,
                     help="selections per signal in each autotuner probe (0: default schedule, no autotuning)")
     ap.add_argument("--eps", type=float, action="append", default=None,
@@ -131,6 +133,8 @@ def main():
                          "noise: 6.04e6 samples of white noise run until the error estimate turns "
                          "negative, at four thresholds")
     args = ap.parse_args()
+    if args.plan_flags is None:
+        args.plan_flags = 0x40 if (args.workload == "c3" and args.study is None) else 0x0
     if args.calib_copy > 0:
         calib_copy(args.calib_copy)
         return
@@ -188,7 +192,7 @@ def main():
     # ---- batched FP32 path: schedule chosen by the autotuner (untimed, like plan creation) ----
     x = torch.from_numpy(np.concatenate(xs).astype(np.float32)).to(dev)
     tune = None
-    if args.probe_atoms > 0 and not (args.plan_flags & (mpg.MP_SCHED_NT512 | mpg.MP_SCHED_G128)):
+    if args.probe_atoms > 0 and not (args.plan_flags & SCHED_FLAGS):
         plan, tune = mpg.Plan.autotuned(wl.dicts, lengths, x, wl.eps, args.plan_flags,
                                         probe_atoms=args.probe_atoms, stream=stream)
         log("autotuned: %s" % tune)
@@ -226,7 +230,7 @@ def main():
     alg_bytes = 16.0 * st.updated + 8.0 * (st.blocks + st.l1_groups)
     achieved = alg_bytes / (loop_ms * 1e-3) / 1e9
     kname = _mp32_name(st, p2)
-    traffic = _traffic(kname, args.workload)
+    traffic = _traffic(_mp32_key(st, p2), args.workload)
     coefs = sum(int(i.n_coefs) for i in infos)
     dgt_bytes = 4.0 * sum(lengths) * len(wl.dicts) + 8.0 * coefs
     dgt_gbps = dgt_bytes / (st.dgt_ms * 1e-3) / 1e9 if st.dgt_ms > 0 else None
@@ -333,11 +337,12 @@ def main():
             "min_snr_db": float(min(snr_reached)),
             "plan_flags": args.plan_flags,
             "analysis_dft": _dft_name(args.plan_flags),
-            "schedule": {"threads": int(st.threads), "group_leaves": int(st.group_leaves), "autotune": tune},
+            "schedule": {"threads": int(st.threads), "group_leaves": int(st.group_leaves),
+                         "tile_rows": int(st.tile_rows), "autotune": tune},
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": kname, "alg_bytes_per_launch": alg_bytes,
+                     "kernel": kname, "tile_rows": int(st.tile_rows), "alg_bytes_per_launch": alg_bytes,
                      "launch_ms": loop_ms, "frac_of_copy": achieved / copy_gbps,
                      "traffic_over_alg": (traffic / alg_bytes) if traffic else None},
         "cpu_baseline": cpu,
@@ -480,7 +485,13 @@ def c5_bench(args):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     x = torch.from_numpy(np.concatenate(xs).astype(np.float32)).to(dev)
-    plan = mpg.Plan(wl.dicts, lengths, wl.eps, args.plan_flags)
+    tune = None
+    if args.probe_atoms > 0 and not (args.plan_flags & SCHED_FLAGS):
+        plan, tune = mpg.Plan.autotuned(wl.dicts, lengths, x, wl.eps, args.plan_flags,
+                                        probe_atoms=args.probe_atoms, stream=stream)
+        log("autotuned: %s" % tune)
+    else:
+        plan = mpg.Plan(wl.dicts, lengths, wl.eps, args.plan_flags)
     log("plan built; warmup")
     for _ in range(args.warmup):
         plan.analyze(x, stream)
@@ -519,10 +530,11 @@ def c5_bench(args):
                    "stop_reasons": {"K": stops[1], "snr": stops[2], "E<0": stops[3], "zero": stops[4]},
                    "min_snr_db": float(min(10 * np.log10(i.E0 / max(i.E, 1e-300)) for i in infos)),
                    "max_snr_db": float(max(10 * np.log10(i.E0 / max(i.E, 1e-300)) for i in infos)),
-                   "schedule": {"threads": int(st.threads), "group_leaves": int(st.group_leaves)}},
+                   "schedule": {"threads": int(st.threads), "group_leaves": int(st.group_leaves),
+                                "tile_rows": int(st.tile_rows), "autotune": tune}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": _traffic(_mp32_name(st), "c5"),
-                     "kernel": _mp32_name(st),
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": _traffic(_mp32_key(st), "c5"),
+                     "kernel": _mp32_name(st), "tile_rows": int(st.tile_rows),
                      "alg_bytes_per_launch": alg_bytes, "launch_ms": lm},
         "mp_loop_atoms_per_s": st.atoms / (lm * 1e-3),
         "dgt": {"ms": float(np.mean(dgt_ms)), "GB_per_s": dgt_bytes / (float(np.mean(dgt_ms)) * 1e-3) / 1e9},
@@ -544,9 +556,20 @@ def calib_copy(nbytes):
     print(json.dumps({"calib_copy_bytes": n * 4, "launches": 3}))
 
 
+SCHED_FLAGS = 0x1000 | 0x2000 | 0x4000 | 0x8000  # MP_SCHED_*
+
+
 def _mp32_name(st, p2=True):
-    """Name of the FP32 loop kernel a plan launches (p2: every M a power of two)."""
-    return "mpg::k_mp32<%d, 2, %d, %s>" % (st.threads, st.group_leaves, "true" if p2 else "false")
+    """Name of the FP32 loop kernel a plan launches (p2: every M a power of two);
+    32-row tiles have a four-slot instantiation, 8- and 16-row tiles share the
+    two-slot one."""
+    return "mpg::k_mp32<%d, %d, %d, %s>" % (st.threads, 4 if st.tile_rows == 32 else 2, st.group_leaves,
+                                            "true" if p2 else "false")
+
+
+def _mp32_key(st, p2=True):
+    """Key of a schedule in the traffic profile: kernel name and tile rows."""
+    return "%s tile%d" % (_mp32_name(st, p2), st.tile_rows)
 
 
 def _traffic(kname, workload="c3"):

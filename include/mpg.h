@@ -84,11 +84,16 @@ extern "C" {
  * have no partner, score |rho|^2. */
 #define MP_PEDANTIC 0x100u
 /* Schedule of the FP32 MP kernel (FP32 plans only).  Default: 768 threads
- * (12 waves) per signal and 256-leaf tree groups, each falling back when the
- * tree groups would not fit the LDS.  The results do not depend on the
- * schedule; mp_autotune picks one by timing. */
+ * (12 waves) per signal, 256-leaf tree groups, 16-row tiles, each falling
+ * back when the tree groups would not fit the LDS.  The tile is the unit of
+ * the neighbourhood split: the 16-bin rows an update touches (its kernel
+ * neighbourhood in every target system) go to the waves from a counter, a
+ * tile per grab.  The results do not depend on the schedule; mp_autotune
+ * picks one by timing. */
 #define MP_SCHED_NT512 0x1000u   /* 512 threads (8 waves) per signal            */
 #define MP_SCHED_G128 0x2000u    /* 128-leaf tree groups                        */
+#define MP_SCHED_TILE8 0x4000u   /* 8-row tiles                                 */
+#define MP_SCHED_TILE32 0x8000u  /* 32-row tiles (with MP_SCHED_NT512 only)     */
 
 /* ---- input sample types for mp_analyze / output types for mp_resynth ---- */
 #define MP_DTYPE_F32 0
@@ -149,6 +154,8 @@ typedef struct {
   double dgt_ms;          /* device time of the DGT kernels in it           */
   int32_t group_leaves;   /* leaves per tree group of the plan              */
   int32_t threads;        /* threads per workgroup of the MP kernel         */
+  int32_t tile_rows;      /* rows per tile of the neighbourhood split       */
+  int32_t pad;
 } mp_stats;
 
 /* Creates a plan for `batch` signals of lengths L[0..batch-1] and the W
@@ -159,7 +166,8 @@ typedef struct {
  * kernel_tol is the threshold epsilon, 0 <= epsilon < 1 (0 keeps every
  * entry whose overlap is nonzero; MP_E_ARG otherwise).  flags: MP_PREC_*, MP_THR_REL,
  * MP_CONJ_GATE_GAMMA, MP_PEDANTIC, at most one MP_DFT_* (not with
- * MP_PREC_F64), MP_SCHED_* (not with MP_PREC_F64).  Uses the
+ * MP_PREC_F64), MP_SCHED_* (not with MP_PREC_F64; at most one MP_SCHED_TILE*,
+ * MP_SCHED_TILE32 only with MP_SCHED_NT512).  Uses the
  * current HIP device; blocks until the kernels are built.  *out receives the
  * plan.  MP_E_LIMIT: a frame's FFT exceeds the LDS of one workgroup (M/2
  * complex entries of the DFT's precision; twice that for the split
@@ -169,26 +177,31 @@ int mp_plan_create(const mp_dict *dicts, int32_t W, const int64_t *L,
                    mp_plan **out);
 
 /* Timings of mp_autotune: one entry per schedule tried. */
+#define MP_TUNE_MAX 10
 typedef struct {
-  int32_t n_cand;          /* schedules tried (distinct launch shapes)       */
-  int32_t chosen;          /* index of the returned one                       */
-  uint32_t flags[4];       /* MP_SCHED_* bits of each                         */
-  int32_t threads[4];      /* threads per workgroup of each                   */
-  int32_t group_leaves[4]; /* leaves per tree group of each                   */
-  double probe_ms[4];      /* device time of each probe run                   */
+  int32_t n_cand;                    /* schedules tried (distinct ones)       */
+  int32_t chosen;                    /* index of the returned one             */
+  uint32_t flags[MP_TUNE_MAX];       /* MP_SCHED_* bits of each               */
+  int32_t threads[MP_TUNE_MAX];      /* threads per workgroup of each         */
+  int32_t group_leaves[MP_TUNE_MAX]; /* leaves per tree group of each         */
+  int32_t tile_rows[MP_TUNE_MAX];    /* rows per neighbourhood tile of each   */
+  double probe_ms[MP_TUNE_MAX];      /* device time of each probe run         */
 } mp_tune_report;
 
 /* Schedule autotuner (no counterpart in the paper: the launch shape of the
  * batched loop is a property of this GPU implementation).  Creates a plan as
  * mp_plan_create(dicts, W, L, batch, kernel_tol, flags | s) for each
- * schedule s among MP_SCHED_* combinations (one schedule for FP64 plans),
- * skips schedules whose plan would duplicate an earlier launch shape or does
- * not fit (MP_E_LIMIT), analyses x_dev (as mp_analyze) and times an mp_run of
- * probe_atoms selections per signal without SNR rule on `stream` (device
- * events; synchronizes).  The schedules are tried in the order default,
- * MP_SCHED_G128, MP_SCHED_NT512, both; a later one replaces the current
- * choice only when its probe is more than 1 % faster, so that timing noise
- * does not flip the choice.  *out receives the chosen plan, the others are
+ * schedule s among the MP_SCHED_* combinations (one schedule for FP64
+ * plans): the four launch shapes (threads x group leaves) with 16- and 8-row
+ * tiles, and the two 512-thread shapes with 32-row tiles.  It skips schedules
+ * whose plan would duplicate an earlier one or does not fit (MP_E_LIMIT),
+ * analyses x_dev (as mp_analyze) and times an mp_run of probe_atoms
+ * selections per signal without SNR rule on `stream` (device events;
+ * synchronizes).  The schedules are tried in the order default, MP_SCHED_G128,
+ * MP_SCHED_NT512, both, then the same with MP_SCHED_TILE8, then the two
+ * MP_SCHED_TILE32 ones; a later one replaces the current choice only when
+ * its probe is more than 1 % faster, so that timing noise does not flip the
+ * choice.  *out receives the chosen plan, the others are
  * destroyed; the returned plan holds the probe's state, so call mp_analyze
  * before using it.  rep (may be null) receives the timings.  Errors:
  * MP_E_ARG for null pointers, probe_atoms <= 0 or MP_SCHED_* bits in flags,

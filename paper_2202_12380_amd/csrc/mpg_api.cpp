@@ -307,13 +307,16 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
   *out = nullptr;
   if (!dicts || !L || W < 1 || W > MAXW || batch < 1 || batch > (1 << 20)) return MP_E_ARG;
   if (!(kernel_tol >= 0.0 && kernel_tol < 1.0)) return MP_E_ARG;
+  constexpr uint32_t SCHED = MP_SCHED_NT512 | MP_SCHED_G128 | MP_SCHED_TILE8 | MP_SCHED_TILE32;
   if (flags & ~(MP_PREC_F64 | MP_THR_REL | MP_CONJ_GATE_GAMMA | MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT | MP_DFT_F64 |
-                MP_PEDANTIC | MP_SCHED_NT512 | MP_SCHED_G128))
+                MP_PEDANTIC | SCHED))
     return MP_E_ARG;
+  if ((flags & MP_SCHED_TILE8) && (flags & MP_SCHED_TILE32)) return MP_E_ARG;
+  if ((flags & MP_SCHED_TILE32) && !(flags & MP_SCHED_NT512)) return MP_E_ARG;  // 4 slots fit 512 threads only
   const uint32_t dftf = flags & (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT);
   const uint32_t dfts = flags & (MP_DFT_F16SPLIT | MP_DFT_BF16SPLIT | MP_DFT_F64);
   if ((dfts & (dfts - 1)) || (dfts && (flags & MP_PREC_F64))) return MP_E_ARG;  // at most one, FP32 plans only
-  if ((flags & MP_PREC_F64) && (flags & (MP_SCHED_NT512 | MP_SCHED_G128))) return MP_E_ARG;
+  if ((flags & MP_PREC_F64) && (flags & SCHED)) return MP_E_ARG;
   int rc = check_dicts(dicts, W);
   if (rc) return rc;
   // the split DFT is a four-step transform over powers of two
@@ -816,10 +819,11 @@ fail:
 int mp_autotune(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t batch, double kernel_tol, uint32_t flags,
                 const void* x_dev, int32_t dtype, int64_t probe_atoms, hipStream_t stream, mp_plan** out,
                 mp_tune_report* rep) {
-  if (!out || !x_dev || probe_atoms <= 0 || (flags & (MP_SCHED_NT512 | MP_SCHED_G128))) return MP_E_ARG;
+  constexpr uint32_t NT = MP_SCHED_NT512, G1 = MP_SCHED_G128, T8 = MP_SCHED_TILE8, T32 = MP_SCHED_TILE32;
+  if (!out || !x_dev || probe_atoms <= 0 || (flags & (NT | G1 | T8 | T32))) return MP_E_ARG;
   *out = nullptr;
-  const uint32_t cands[4] = {0u, MP_SCHED_G128, MP_SCHED_NT512, MP_SCHED_NT512 | MP_SCHED_G128};
-  const int ncand = (flags & MP_PREC_F64) ? 1 : 4;
+  const uint32_t cands[MP_TUNE_MAX] = {0u, G1, NT, NT | G1, T8, G1 | T8, NT | T8, NT | G1 | T8, NT | T32, NT | G1 | T32};
+  const int ncand = (flags & MP_PREC_F64) ? 1 : MP_TUNE_MAX;
   mp_tune_report r;
   memset(&r, 0, sizeof(r));
   r.chosen = -1;
@@ -833,9 +837,11 @@ int mp_autotune(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t batch
       mp_plan_destroy(best);
       return rc;
     }
-    bool dup = false;  // a preference that fell back to an earlier launch shape
+    mp_stats s0;
+    (void)mp_get_stats(p, &s0);  // launch shape and tile of the plan (no device work before analysis)
+    bool dup = false;  // a preference that fell back to an earlier schedule
     for (int i = 0; i < r.n_cand; ++i)
-      if (r.threads[i] == p->nt && r.group_leaves[i] == p->G) dup = true;
+      if (r.threads[i] == p->nt && r.group_leaves[i] == p->G && r.tile_rows[i] == s0.tile_rows) dup = true;
     if (dup) {
       mp_plan_destroy(p);
       continue;
@@ -854,6 +860,7 @@ int mp_autotune(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t batch
     r.flags[i] = cands[c];
     r.threads[i] = p->nt;
     r.group_leaves[i] = p->G;
+    r.tile_rows[i] = st.tile_rows;
     r.probe_ms[i] = st.loop_ms;
     if (!best || st.loop_ms < 0.99 * best_ms) {  // more than 1 % faster: noise does not flip the choice
       mp_plan_destroy(best);
@@ -919,6 +926,8 @@ static MPArgs mp_args(const mp_plan* p, int64_t max_atoms, double target_snr_db)
   a.gammas = p->f64 ? (const void*)p->d_gam64 : (const void*)p->d_gam32;
   a.roots = p->f64 ? (const void*)p->d_root64 : (const void*)p->d_root32;
   a.n_groups_max = p->n_groups_max;
+  a.slot_cap = (p->flags & MP_SCHED_TILE8) ? 1 : ((p->flags & MP_SCHED_TILE32) ? 4 : 2);
+  a.pad3 = 0;
   a.p2 = 1;
   for (int w = 0; w < p->W; ++w)
     if (!is_pow2(p->hd[w].M)) a.p2 = 0;
@@ -1170,6 +1179,7 @@ int mp_get_stats(const mp_plan* p, mp_stats* out) {
   memset(out, 0, sizeof(*out));
   out->group_leaves = p->G;
   out->threads = p->nt;
+  out->tile_rows = p->f64 ? 0 : ((p->flags & MP_SCHED_TILE8) ? 8 : ((p->flags & MP_SCHED_TILE32) ? 32 : 16));
   if (!p->analyzed) return MP_OK;
   if (hipStreamSynchronize(p->last_stream) != hipSuccess) return MP_E_HIP;
   std::vector<SigState> st((size_t)p->batch);

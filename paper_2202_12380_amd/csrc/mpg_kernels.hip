@@ -2788,7 +2788,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     // this wave's row stores.
     {
       const int nslots = T_items >> 3;
-      const int bs = min(SLOTS, max(1, (nslots + NW - 2) / (NW - 1)));
+      const int bs = min(min(SLOTS, A.slot_cap), max(1, (nslots + NW - 2) / (NW - 1)));
       int qb = grab() * bs;
       if (qb < nslots) {
         do {
@@ -3334,12 +3334,17 @@ hipError_t launch_mp(bool f64, int nt, const MPArgs& a, int grid, hipStream_t st
     if (nt != 512) return hipErrorInvalidValue;
     return launch_mp_t<double, 512, 4>(a, grid, preload, st);
   }
+  // tiles of 1 or 2 slots run the two-slot kernel with a cap; 4 slots (512
+  // threads only) have their own
+  if (a.slot_cap == 4 && nt != 512) return hipErrorInvalidValue;
   if (a.G == 128) {
     if (nt == 768) return launch_mp32_p<768, 2, 128>(a, grid, st);
+    if (a.slot_cap == 4) return launch_mp32_p<512, 4, 128>(a, grid, st);
     return launch_mp32_p<512, 2, 128>(a, grid, st);
   }
   if (a.G == 256) {
     if (nt == 768) return launch_mp32_p<768, 2, 256>(a, grid, st);
+    if (a.slot_cap == 4) return launch_mp32_p<512, 4, 256>(a, grid, st);
     return launch_mp32_p<512, 2, 256>(a, grid, st);
   }
   return hipErrorInvalidValue;

@@ -23,6 +23,8 @@ MP_DFT_F16SPLIT, MP_DFT_BF16SPLIT = 0x40, 0x80
 MP_DFT_F32, MP_DFT_F64 = 0x0, 0x200
 MP_PEDANTIC = 0x100
 MP_SCHED_NT512, MP_SCHED_G128 = 0x1000, 0x2000
+MP_SCHED_TILE8, MP_SCHED_TILE32 = 0x4000, 0x8000
+MP_TUNE_MAX = 10
 MP_DTYPE_F32, MP_DTYPE_F64 = 0, 1
 MP_STATIC_RESYNTH_MAX = 1 << 22
 MP_STOP_NONE, MP_STOP_K, MP_STOP_SNR, MP_STOP_ENEG, MP_STOP_ZERO = range(5)
@@ -54,21 +56,24 @@ class mp_kernel_info(C.Structure):
 
 
 class mp_tune_report(C.Structure):
-    _fields_ = [("n_cand", C.c_int32), ("chosen", C.c_int32), ("flags", C.c_uint32 * 4),
-                ("threads", C.c_int32 * 4), ("group_leaves", C.c_int32 * 4), ("probe_ms", C.c_double * 4)]
+    _fields_ = [("n_cand", C.c_int32), ("chosen", C.c_int32), ("flags", C.c_uint32 * MP_TUNE_MAX),
+                ("threads", C.c_int32 * MP_TUNE_MAX), ("group_leaves", C.c_int32 * MP_TUNE_MAX),
+                ("tile_rows", C.c_int32 * MP_TUNE_MAX), ("probe_ms", C.c_double * MP_TUNE_MAX)]
 
     def as_dict(self):
         n = self.n_cand
         return {"chosen": self.chosen,
                 "schedules": [{"flags": int(self.flags[i]), "threads": int(self.threads[i]),
-                               "group_leaves": int(self.group_leaves[i]), "probe_ms": float(self.probe_ms[i])}
+                               "group_leaves": int(self.group_leaves[i]), "tile_rows": int(self.tile_rows[i]),
+                               "probe_ms": float(self.probe_ms[i])}
                               for i in range(n)]}
 
 
 class mp_stats(C.Structure):
     _fields_ = [("atoms", C.c_int64), ("updated", C.c_int64), ("blocks", C.c_int64),
                 ("l1_groups", C.c_int64), ("loop_ms", C.c_double), ("analyze_ms", C.c_double),
-                ("dgt_ms", C.c_double), ("group_leaves", C.c_int32), ("threads", C.c_int32)]
+                ("dgt_ms", C.c_double), ("group_leaves", C.c_int32), ("threads", C.c_int32),
+                ("tile_rows", C.c_int32), ("pad", C.c_int32)]
 
 
 EXPORTS = ["mp_plan_create", "mp_analyze", "mp_run", "mp_run_resets",

@@ -54,7 +54,10 @@ def test_strerror_and_argument_errors_without_gpu():
         ([(0, 64, 16, 64)], [1024], 1e-4, 0x41, mpg.MP_E_ARG),                  # split DFT with FP64
         ([(0, 64, 16, 64)], [1024], 1e-4, 0xC0, mpg.MP_E_ARG),                  # two DFT formats
         ([(0, 64, 16, 64)], [1024], 1e-4, 0x1001, mpg.MP_E_ARG),                # FP32 schedule on an FP64 plan
-        ([(0, 64, 16, 64)], [1024], 1e-4, 0x4000, mpg.MP_E_ARG),                # unknown schedule bit
+        ([(0, 64, 16, 64)], [1024], 1e-4, 0x10000, mpg.MP_E_ARG),               # unknown flag bit
+        ([(0, 64, 16, 64)], [1024], 1e-4, 0xC000, mpg.MP_E_ARG),                # two tile sizes
+        ([(0, 64, 16, 64)], [1024], 1e-4, 0x8000, mpg.MP_E_ARG),                # 32-row tiles need 512 threads
+        ([(0, 64, 16, 64)], [1024], 1e-4, 0x4001, mpg.MP_E_ARG),                # tile on an FP64 plan
     ]
     for dicts, lens, eps, flags, code in cases:
         with pytest.raises(mpg.MPError) as e:
@@ -75,8 +78,8 @@ def test_strerror_and_argument_errors_without_gpu():
     assert L.mp_autotune(arr, 1, Ls, 1, 1e-4, 0, fake_x, 0, 100, None, None, None) == mpg.MP_E_ARG
     assert L.mp_autotune(arr, 1, Ls, 1, 1e-4, 0, None, 0, 100, None, C.byref(out), None) == mpg.MP_E_ARG
     assert L.mp_autotune(arr, 1, Ls, 1, 1e-4, 0, fake_x, 0, 0, None, C.byref(out), None) == mpg.MP_E_ARG
-    assert L.mp_autotune(arr, 1, Ls, 1, 1e-4, mpg.MP_SCHED_NT512, fake_x, 0, 100, None, C.byref(out),
-                         None) == mpg.MP_E_ARG
+    for f in (mpg.MP_SCHED_NT512, mpg.MP_SCHED_TILE8, mpg.MP_SCHED_TILE32):
+        assert L.mp_autotune(arr, 1, Ls, 1, 1e-4, f, fake_x, 0, 100, None, C.byref(out), None) == mpg.MP_E_ARG
     assert out.value is None
 
 

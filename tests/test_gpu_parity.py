@@ -379,51 +379,55 @@ def test_mp_fp32_gcd_grids():
         assert_tolerance(ga[i], orc)
 
 
-@pytest.mark.parametrize("sched,threads,groups", [
-    (0x1000, 512, 256),                  # MP_SCHED_NT512: the LDS fallback launch shape
-    (0x2000, 768, 128),                  # MP_SCHED_G128: 128-leaf groups
+@pytest.mark.parametrize("sched,threads,groups,tile", [
+    (0x1000, 512, 256, 16),              # MP_SCHED_NT512: the LDS fallback launch shape
+    (0x2000, 768, 128, 16),              # MP_SCHED_G128: 128-leaf groups
+    (0x4000, 768, 256, 8),               # MP_SCHED_TILE8: 8-row tiles
+    (0x9000, 512, 256, 32),              # MP_SCHED_NT512 | MP_SCHED_TILE32: 32-row tiles
 ])
-def test_mp_fp32_launch_shapes(sched, threads, groups):
-    # the plan's other FP32 launch shapes give the same atoms within the FP32 rule
+def test_mp_fp32_launch_shapes(sched, threads, groups, tile):
+    # the plan's other FP32 schedules give the same atoms within the FP32 rule
     _torch()
     dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)]
     lens = [16384, 12345]
     xs = [S.audio_like(L, S.rng(80, i)).astype(np.float32) for i, L in enumerate(lens)]
     plan, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=sched)
     st = plan.stats()
-    assert (st.threads, st.group_leaves) == (threads, groups)
+    assert (st.threads, st.group_leaves, st.tile_rows) == (threads, groups, tile)
     for i, x in enumerate(xs):
         orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32)
         assert_tolerance(ga[i], orc)
 
 
 def test_mp_fp32_schedules_identical_and_autotune():
-    # every FP32 schedule (threads per signal, leaves per tree group) gives the
-    # same atoms bit for bit; the autotuner returns one of them, usable after a
-    # fresh analysis
+    # every FP32 schedule (threads per signal, leaves per tree group, rows per
+    # neighbourhood tile) gives the same atoms bit for bit; the autotuner
+    # returns one of them, usable after a fresh analysis
     torch = _torch()
     from paper_2202_12380_amd import mpg
     dicts = [(0, 256, 64, 256), (0, 1024, 256, 1024), (0, 4096, 1024, 4096)]
     lens = [16384, 9000, 12345]
     xs = [S.audio_like(L, S.rng(81, i)).astype(np.float32) for i, L in enumerate(lens)]
+    NT, G1, T8, T32 = mpg.MP_SCHED_NT512, mpg.MP_SCHED_G128, mpg.MP_SCHED_TILE8, mpg.MP_SCHED_TILE32
     runs = {}
-    for f in (0, mpg.MP_SCHED_G128, mpg.MP_SCHED_NT512, mpg.MP_SCHED_NT512 | mpg.MP_SCHED_G128):
+    for f in (0, G1, NT, NT | G1, T8, G1 | T8, NT | T8, NT | G1 | T8, NT | T32, NT | G1 | T32):
         plan, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=f)
         st = plan.stats()
-        runs[(st.threads, st.group_leaves)] = ga
-    assert set(runs) == {(768, 256), (768, 128), (512, 256), (512, 128)}
-    ref = runs[(768, 256)]
+        runs[(st.threads, st.group_leaves, st.tile_rows)] = ga
+    assert set(runs) == {(768, 256, 16), (768, 128, 16), (512, 256, 16), (512, 128, 16), (768, 256, 8),
+                         (768, 128, 8), (512, 256, 8), (512, 128, 8), (512, 256, 32), (512, 128, 32)}
+    ref = runs[(768, 256, 16)]
     for shape, ga in runs.items():
         for a, b in zip(ga, ref):
             assert len(a) == len(b), shape
             assert np.array_equal(a, b), shape
     x = torch.from_numpy(np.concatenate(xs)).cuda()
     plan, rep = mpg.Plan.autotuned(dicts, lens, x, 1e-4, 0, probe_atoms=300)
-    assert 1 <= len(rep["schedules"]) <= 4 and 0 <= rep["chosen"] < len(rep["schedules"])
+    assert len(rep["schedules"]) == 10 and 0 <= rep["chosen"] < 10
     assert all(s["probe_ms"] > 0 for s in rep["schedules"])
     st = plan.stats()
     ch = rep["schedules"][rep["chosen"]]
-    assert (st.threads, st.group_leaves) == (ch["threads"], ch["group_leaves"])
+    assert (st.threads, st.group_leaves, st.tile_rows) == (ch["threads"], ch["group_leaves"], ch["tile_rows"])
     assert all(len(plan.atoms(s)) == 300 for s in range(len(lens)))  # the probe's state
     plan.analyze(x)
     plan.run(0, 25.0)
