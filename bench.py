@@ -195,6 +195,7 @@ def main():
     if args.probe_atoms > 0 and not (args.plan_flags & SCHED_FLAGS):
         plan, tune = mpg.Plan.autotuned(wl.dicts, lengths, x, wl.eps, args.plan_flags,
                                         probe_atoms=args.probe_atoms, stream=stream)
+        _probe_roofline(tune)
         log("autotuned: %s" % tune)
     else:
         plan = mpg.Plan(wl.dicts, lengths, wl.eps, args.plan_flags)
@@ -489,6 +490,7 @@ def c5_bench(args):
     if args.probe_atoms > 0 and not (args.plan_flags & SCHED_FLAGS):
         plan, tune = mpg.Plan.autotuned(wl.dicts, lengths, x, wl.eps, args.plan_flags,
                                         probe_atoms=args.probe_atoms, stream=stream)
+        _probe_roofline(tune)
         log("autotuned: %s" % tune)
     else:
         plan = mpg.Plan(wl.dicts, lengths, wl.eps, args.plan_flags)
@@ -557,6 +559,15 @@ def calib_copy(nbytes):
 
 
 SCHED_FLAGS = 0x1000 | 0x2000 | 0x4000 | 0x8000  # MP_SCHED_*
+
+
+def _probe_roofline(tune):
+    """Adds each autotuner probe's algorithmic HBM rate and its fraction of
+    the 8 TB/s peak to the report."""
+    for sc in tune["schedules"]:
+        gbps = sc["probe_bytes"] / (sc["probe_ms"] * 1e-3) / 1e9 if sc["probe_ms"] > 0 else None
+        sc["probe_GB_per_s"] = gbps
+        sc["probe_roofline_frac"] = gbps / HBM_PEAK_GBPS if gbps else None
 
 
 def _mp32_name(st, p2=True):

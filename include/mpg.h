@@ -186,6 +186,10 @@ typedef struct {
   int32_t group_leaves[MP_TUNE_MAX]; /* leaves per tree group of each         */
   int32_t tile_rows[MP_TUNE_MAX];    /* rows per neighbourhood tile of each   */
   double probe_ms[MP_TUNE_MAX];      /* device time of each probe run         */
+  double probe_bytes[MP_TUNE_MAX];   /* algorithmic bytes of each probe: 16 B per
+                                        coefficient update with a nonzero kernel
+                                        entry + 8 B per tree leaf and group
+                                        rewritten (FP32 plans; FP64: 32 B)  */
 } mp_tune_report;
 
 /* Schedule autotuner (no counterpart in the paper: the launch shape of the

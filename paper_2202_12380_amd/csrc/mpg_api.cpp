@@ -862,6 +862,7 @@ int mp_autotune(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t batch
     r.group_leaves[i] = p->G;
     r.tile_rows[i] = st.tile_rows;
     r.probe_ms[i] = st.loop_ms;
+    r.probe_bytes[i] = (p->f64 ? 32.0 : 16.0) * (double)st.updated + 8.0 * (double)(st.blocks + st.l1_groups);
     if (!best || st.loop_ms < 0.99 * best_ms) {  // more than 1 % faster: noise does not flip the choice
       mp_plan_destroy(best);
       best = p;

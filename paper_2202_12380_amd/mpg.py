@@ -58,14 +58,15 @@ class mp_kernel_info(C.Structure):
 class mp_tune_report(C.Structure):
     _fields_ = [("n_cand", C.c_int32), ("chosen", C.c_int32), ("flags", C.c_uint32 * MP_TUNE_MAX),
                 ("threads", C.c_int32 * MP_TUNE_MAX), ("group_leaves", C.c_int32 * MP_TUNE_MAX),
-                ("tile_rows", C.c_int32 * MP_TUNE_MAX), ("probe_ms", C.c_double * MP_TUNE_MAX)]
+                ("tile_rows", C.c_int32 * MP_TUNE_MAX), ("probe_ms", C.c_double * MP_TUNE_MAX),
+                ("probe_bytes", C.c_double * MP_TUNE_MAX)]
 
     def as_dict(self):
         n = self.n_cand
         return {"chosen": self.chosen,
                 "schedules": [{"flags": int(self.flags[i]), "threads": int(self.threads[i]),
                                "group_leaves": int(self.group_leaves[i]), "tile_rows": int(self.tile_rows[i]),
-                               "probe_ms": float(self.probe_ms[i])}
+                               "probe_ms": float(self.probe_ms[i]), "probe_bytes": float(self.probe_bytes[i])}
                               for i in range(n)]}
 
 
