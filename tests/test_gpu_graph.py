@@ -10,7 +10,9 @@ from paper_2202_12380_amd import signals as S
 pytestmark = pytest.mark.gpu
 
 
-def test_captured_analysis_and_loop_replay_like_eager():
+@pytest.mark.parametrize("flags", [0x40, 0x0])
+def test_captured_analysis_and_loop_replay_like_eager(flags):
+    # analysis in FP16 pairs on matrix cores (0x40, as benchmarked) or the FP32 FFT
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_2202_12380_amd import mpg
@@ -18,7 +20,7 @@ def test_captured_analysis_and_loop_replay_like_eager():
     lens = [16384, 9000, 20000, 12288]
     xs = [S.audio_like(L, S.rng(95, i)).astype(np.float32) for i, L in enumerate(lens)]
     x = torch.from_numpy(np.concatenate(xs)).cuda()
-    plan = mpg.Plan(dicts, lens, 1e-4, 0)
+    plan = mpg.Plan(dicts, lens, 1e-4, flags)
     K, snr = 4000, 30.0
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
