@@ -277,7 +277,15 @@ def main():
     if args.fp64_sample > 0:
         tot_atoms, tot_ms = 0, 0.0
         same64, gap64 = [], []
-        for i in range(min(args.fp64_sample, len(xs))):
+        # signals the oracle also ran (spread over their length ranks), so that
+        # the FP64 sequences are checked against it; else the first ones
+        if orc:
+            ko = sorted(orc, key=lambda i: lengths[i])
+            n64 = min(args.fp64_sample, len(ko))
+            pick64 = [ko[round(t * (len(ko) - 1) / max(n64 - 1, 1))] for t in range(n64)]
+        else:
+            pick64 = list(range(min(args.fp64_sample, len(xs))))
+        for i in pick64:
             p64 = mpg.Plan(wl.dicts, [lengths[i]], wl.eps, mpg.MP_PREC_F64)
             x64 = torch.from_numpy(xs[i].astype(np.float64)).to(dev)
             p64.analyze(x64, stream)
@@ -294,7 +302,7 @@ def main():
                     (ga["w"] == r["w"]) & (ga["m"] == r["m"]) & (ga["n"] == r["n"]))))
                 gap64.append(float(np.min(r["gap"][:r["n_atoms"]])) if r["n_atoms"] else None)
             p64.close()
-        fp64 = dict(atoms_per_s=tot_atoms / (tot_ms * 1e-3), signals=min(args.fp64_sample, len(xs)),
+        fp64 = dict(atoms_per_s=tot_atoms / (tot_ms * 1e-3), signals=pick64,
                     atoms=tot_atoms, loop_ms=tot_ms,
                     identical_to_oracle=same64 if same64 else None,
                     smallest_top2_gap=min(g for g in gap64 if g is not None) if any(
