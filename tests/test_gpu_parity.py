@@ -352,7 +352,7 @@ def test_mp_precision_study_batch(fmt, eps):
 # (analysis format, threshold, signal) of the precision-study batch whose FP32
 # loop leaves the oracle's sequence at a top-2 gap above 1e-6 but within the
 # floor of the measured coefficient error (gpu_helpers.fp32_gap_floor)
-PRECISION_FLOOR_CASES = {(0x40, 1e-3, 1), (0x40, 1e-3, 2), (0x40, 1e-5, 2)}
+PRECISION_FLOOR_CASES = {(0x40, 1e-5, 2)}
 
 
 def test_mp_fp32_gaussian_long_windows():
