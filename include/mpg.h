@@ -73,7 +73,9 @@ extern "C" {
  * and rounds the coefficients to the plan's FP32 (systems need M <= 16384).
  * The split variants run the DFT on matrix cores as a four-step transform
  * with each operand a pair of half-precision numbers (hi + lo; products
- * hi*hi + hi*lo + lo*hi accumulated in FP32); systems need M <= 16384. */
+ * hi*hi + hi*lo + lo*hi accumulated in FP32; for M = 256 .. 4096 the lo half
+ * holds the remainder scaled by 2^11, which keeps FP16 pairs as accurate as
+ * the FP32 FFT); systems need M a power of two, M <= 16384. */
 #define MP_DFT_F32 0x0u          /* FFT in FP32 (default)                           */
 #define MP_DFT_F64 0x200u        /* FFT in FP64, coefficients rounded to FP32        */
 #define MP_DFT_F16SPLIT 0x40u    /* FP16 pairs                                      */
