@@ -150,8 +150,8 @@ def test_dgt_planes_split_mfma(fmt, tol, dicts, L):
 
 
 @pytest.mark.parametrize("fmt,tol", [(0x40, 3e-6), (0x80, 5e-5)])
-@pytest.mark.parametrize("pedantic", [False, True])
-def test_dgt_planes_split_mfma_batch(fmt, tol, pedantic):
+@pytest.mark.parametrize("pedantic,x64", [(False, False), (True, False), (False, True)])
+def test_dgt_planes_split_mfma_batch(fmt, tol, pedantic, x64):
     # every frame-group shape of the matrix-core DFT (M = 256 .. 4096, 8 .. 1
     # frames per wave) on a batch of uneven lengths, so that frame groups
     # straddle signals, with a folded Gaussian window (gl = 2 M); planes
@@ -166,7 +166,8 @@ def test_dgt_planes_split_mfma_batch(fmt, tol, pedantic):
     xs = [rng.standard_normal(L).astype(np.float32).astype(np.float64) for L in lens]
     flags = fmt | (mpg.MP_PEDANTIC if pedantic else 0)
     plan = mpg.Plan(dicts, lens, 1e-4, flags)
-    plan.analyze(torch.from_numpy(np.concatenate(xs)).to(torch.float32).cuda())
+    # x64: FP64 samples (the path the reset procedure's residual takes)
+    plan.analyze(torch.from_numpy(np.concatenate(xs)).to(torch.float64 if x64 else torch.float32).cuda())
     planes = []
     for s_, (L, v) in enumerate(zip(lens, xs)):
         Lp = O.padded_length(dicts, L)
@@ -590,15 +591,17 @@ def test_resets_fp64_identical(eps, reset_it):
         assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
 
 
-@pytest.mark.parametrize("dft", ["f32", "f64"])
+@pytest.mark.parametrize("dft", ["f32", "f64", "f16pairs"])
 def test_resets_fp32_batch_reach_true_target(dft):
-    # dft f64: the re-analyses of the true residual run the FP64 DFT too
+    # dft f64: the re-analyses of the true residual run the FP64 DFT too;
+    # f16pairs: they run the split DFT on matrix cores from the FP64 residual
     torch = _torch()
     from paper_2202_12380_amd import mpg
     dicts = [(0, 64, 16, 64), (0, 256, 64, 256)]
     lens = [2048, 3000, 4096]
     xs = [np.random.default_rng(20 + i).standard_normal(L).astype(np.float32) for i, L in enumerate(lens)]
-    plan = mpg.Plan(dicts, lens, 5e-2, mpg.MP_DFT_F64 if dft == "f64" else 0)
+    flags = {"f32": 0, "f64": mpg.MP_DFT_F64, "f16pairs": mpg.MP_DFT_F16SPLIT}[dft]
+    plan = mpg.Plan(dicts, lens, 5e-2, flags)
     plan.analyze(torch.from_numpy(np.concatenate(xs)).cuda())
     plan.run_resets(100000, 30.0, 200, -6.0)
     for s, x in enumerate(xs):
