@@ -235,6 +235,7 @@ def main():
     coefs = sum(int(i.n_coefs) for i in infos)
     dgt_bytes = 4.0 * sum(lengths) * len(wl.dicts) + 8.0 * coefs
     dgt_gbps = dgt_bytes / (st.dgt_ms * 1e-3) / 1e9 if st.dgt_ms > 0 else None
+    dgt_flop = _split_dft_flop(wl.dicts, [int(i.L_padded) for i in infos]) if args.plan_flags & 0xC0 else None
 
     # ---- accuracy of the sampled signals against the oracle ----
     acc = None
@@ -359,7 +360,11 @@ def main():
         "analyze_ms": analyze_ms,
         "dgt": {"ms": st.dgt_ms, "GB_per_s": dgt_gbps, "bytes": dgt_bytes,
                 "frac_of_peak": (dgt_gbps / HBM_PEAK_GBPS) if dgt_gbps else None,
-                "frac_of_copy": (dgt_gbps / copy_gbps) if dgt_gbps else None},
+                "frac_of_copy": (dgt_gbps / copy_gbps) if dgt_gbps else None,
+                "mfma_flop": dgt_flop,
+                "mfma_TFLOP_per_s": (dgt_flop / (st.dgt_ms * 1e-3) / 1e12) if dgt_flop and st.dgt_ms > 0 else None,
+                "frac_of_fp16_peak": (dgt_flop / (st.dgt_ms * 1e-3) / 1e12 / FP16_PEAK_TFLOPS)
+                if dgt_flop and st.dgt_ms > 0 else None},
         "copy_GB_per_s": copy_gbps,
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (loop_rate / fp64["atoms_per_s"]) if fp64 else None,
@@ -567,6 +572,24 @@ def calib_copy(nbytes):
 
 
 SCHED_FLAGS = 0x1000 | 0x2000 | 0x4000 | 0x8000  # MP_SCHED_*
+FP16_PEAK_TFLOPS = 2500.0  # dense FP16 / BF16 MFMA peak of one MI355X
+
+
+def _split_dft_flop(dicts, padded_lengths):
+    """Algorithmic MFMA work of the split DFT over a batch: per frame two complex
+    GEMMs of the four-step transform H = N1 N2 (N1 = 2^ceil(log2(H)/2), both
+    padded to 16), each complex product 4 real products of 3 half-precision
+    MFMA terms (hi hi, hi lo, lo hi): 24 N1 N2 (N2 + N1) flop."""
+    tot = 0.0
+    for _, gl, a, M in dicts:
+        H = M // 2
+        lh = H.bit_length() - 1
+        n1 = 1 << ((lh + 1) // 2)
+        n2 = H // n1
+        n1, n2 = max(n1, 16), max(n2, 16)
+        frames = sum(Lp // a for Lp in padded_lengths)
+        tot += frames * 24.0 * n1 * n2 * (n2 + n1)
+    return tot
 
 
 def _probe_roofline(tune):
