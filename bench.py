@@ -369,6 +369,7 @@ def main():
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (loop_rate / fp64["atoms_per_s"]) if fp64 else None,
         "accuracy_vs_oracle": acc,
+        "paper_context": PAPER_CPU_CONTEXT,
         "counters": {"updated": int(st.updated), "blocks": int(st.blocks), "groups": int(st.l1_groups)},
     }
     print(json.dumps(out))
@@ -572,6 +573,15 @@ def calib_copy(nbytes):
 
 
 SCHED_FLAGS = 0x1000 | 0x2000 | 0x4000 | 0x8000  # MP_SCHED_*
+# The paper's own timings (its timing table and the multi-Gabor line below it):
+# context only, on other hardware and another signal, so vs_baseline is null.
+PAPER_CPU_CONTEXT = {
+    "hardware": "Intel Core i5-4570 (3.2 GHz), one thread, FP64, FFTW 3.3, GCC -Ofast",
+    "signal": "SQAM track 39 (piano, about 6e6 samples), 180000 selections, Blackman windows of length M",
+    "single_system_a_M_over_4_atoms_per_s": [174.8e3, 195.7e3],
+    "five_systems_512_to_8192_a_M_over_4_atoms_per_s": 17.0e3,
+    "five_systems_512_to_8192_a_M_over_4_mptk_atoms_per_s": 1.27e3,
+}
 FP16_PEAK_TFLOPS = 2500.0  # dense FP16 / BF16 MFMA peak of one MI355X
 
 
