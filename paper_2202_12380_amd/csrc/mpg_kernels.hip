@@ -711,7 +711,10 @@ __global__ void __launch_bounds__(256) k_dgt(const XT* __restrict__ x, const Sig
 // with w_N = exp(-2 pi i / N).  The DFT matrices come split and already laid
 // out per MFMA operand (k_dft_tables); N1, N2 <= 128, padded with zeros to
 // multiples of 16.  The frame is scaled by a power of two to max |z| <= 1
-// before the split, so FP16 neither overflows nor loses the low part.
+// before the split, so FP16 does not overflow.  This form (one workgroup per
+// frame, unscaled lo halves) serves the sizes the frame-group kernel below
+// does not: M <= 128 and M >= 8192, and signals whose sample byte offsets
+// need more than 31 bits.
 
 typedef short mf_s4 __attribute__((ext_vector_type(4)));
 typedef _Float16 mf_h4 __attribute__((ext_vector_type(4)));
@@ -1011,9 +1014,9 @@ __global__ void __launch_bounds__(256) k_dgt_mfma(const XT* __restrict__ x, cons
 // The same split-precision DGT for H = M/2 = 128 .. 2048, one wave per group
 // of frames, each wave looping over many groups.  A wave stacks FPW = 64 / N1
 // frames into the 64 rows (frame, n1) of the first GEMM; the DFT matrices
-// (split planes re_hi, re_lo, im_hi, im_lo in MFMA operand order) and the
-// twiddles w_H^{n1 k2} of every (n1, k2) tile are staged in LDS once per
-// workgroup.  A 16x16 MFMA result tile (lane: column, four consecutive rows)
+// (hi planes and 2^11-scaled lo planes of re and im, in MFMA operand order),
+// the twiddles w_H^{n1 k2} of every (n1, k2) tile, the unpacking twiddles and
+// the window are staged in LDS once per workgroup.  A 16x16 MFMA result tile (lane: column, four consecutive rows)
 // has the lane layout of a 16x16x16 B operand (lane: column, four
 // consecutive k), so B(n1, k2) passes from the first GEMM to the second in
 // registers, after its twiddle and split.  Z goes through a per-wave LDS
