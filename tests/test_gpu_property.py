@@ -91,3 +91,49 @@ def test_random_configs_fp32_rule(cfg):
             fm, k_meas)
     if fm:
         assert np.max(np.abs(ga[0]["E_after"][:fm] - orc.E[:fm])) <= 1e-5 * orc.E0
+
+
+@st.composite
+def _split_dft_systems(draw):
+    # one to three systems of M = 256 .. 4096 (the frame-group split DFT's
+    # shapes), any window, windows from M/4 to 2M, hops dividing M or not;
+    # a batch of one to three ragged signals
+    W = draw(st.integers(1, 3))
+    dicts = []
+    while len(dicts) < W:
+        M = 2 ** draw(st.integers(8, 12))
+        gl = 2 * draw(st.integers(M // 8, M))
+        a = draw(st.sampled_from(sorted({M // 8, M // 4, M // 2, 3 * M // 8})))
+        d = (draw(st.integers(0, 2)), gl, a, M)
+        if d not in dicts:
+            dicts.append(d)
+    lens = draw(st.lists(st.integers(256, 12000), min_size=1, max_size=3))
+    return dicts, lens, draw(st.integers(0, 2 ** 31 - 1)), draw(st.sampled_from([0x40, 0x80]))
+
+
+@settings(max_examples=15, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.filter_too_much])
+@given(_split_dft_systems())
+def test_random_configs_split_dft_planes(cfg):
+    # planes of the split DFT on matrix cores against the oracle's DGT, element
+    # by element, relative to each plane's maximum (FP16 pairs 3e-6, BF16 5e-5)
+    torch = pytest.importorskip("torch")
+    from paper_2202_12380_amd import mpg
+    dicts, lens, seed, fmt = cfg
+    Lp = [O.padded_length(dicts, L) for L in lens]
+    if min(Lp) < 0 or max(Lp) > 65536:
+        return
+    print("split dft case", dicts, lens, seed, hex(fmt), flush=True)
+    xs = [np.random.default_rng(seed + i).standard_normal(L).astype(np.float32).astype(np.float64)
+          for i, L in enumerate(lens)]
+    plan = mpg.Plan(dicts, lens, 1e-4, fmt)
+    plan.analyze(torch.from_numpy(np.concatenate(xs)).to(torch.float32).cuda())
+    tol = 3e-6 if fmt == 0x40 else 5e-5
+    for s_, (L, v) in enumerate(zip(lens, xs)):
+        xp = np.zeros(Lp[s_])
+        xp[:L] = v
+        for w, d in enumerate(dicts):
+            ref = O.dgt(d, xp)
+            got = plan.residual(s_, w).cpu().numpy()
+            assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max(), (dicts, lens, s_, w)
+    plan.close()
