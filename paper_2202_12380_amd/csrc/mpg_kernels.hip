@@ -153,6 +153,9 @@ __device__ __forceinline__ int uni_i(int v) { return __builtin_amdgcn_readfirstl
 __device__ __forceinline__ int64_t uni_l(int64_t v) {
   return (int64_t)(((uint64_t)(uint32_t)uni_i((int)(v >> 32)) << 32) | (uint32_t)uni_i((int)v));
 }
+__device__ __forceinline__ double uni_d(double v) {
+  return __builtin_bit_cast(double, uni_l(__builtin_bit_cast(int64_t, v)));
+}
 
 // DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror:4, row_ror:8.
 // Applied in sequence with a max they leave every lane holding its row maximum.
@@ -2291,9 +2294,9 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   __syncthreads();
 
   SigState st = A.state[s];
-  double E = st.E;
-  int64_t k = st.k;
-  const double E0 = st.E0;
+  double E = uni_d(st.E);  // the loop state is uniform: its stop tests branch on scalars
+  int64_t k = uni_l(st.k);
+  const double E0 = uni_d(st.E0);
   int64_t K = A.K > 0 ? A.K : S.Lp / 5;
   if (K > S.cap) K = S.cap;
   double Etarget = A.snr_db > 0.0 ? E0 * exp10(-A.snr_db / 10.0) : -__builtin_huge_val();
@@ -2355,7 +2358,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     // FP32 row keeps that entry at d_t of phase ph_t's part.
     const int k1 = kr + P.mulo, k2 = P.mulo - kr, mspan = P.muhi - P.mulo;
     int ph1, ph2, c1, c2;
-    if (P.rw_sh >= 0) {
+    if (P2 || P.rw_sh >= 0) {  // every M a power of two: so is r_w = M_max / M_w
       ph1 = (-k1) & (P.rw - 1);
       ph2 = (-k2) & (P.rw - 1);
       c1 = (k1 + ph1) >> P.rw_sh;  // exact multiples of r_w
@@ -2392,7 +2395,8 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
 #pragma unroll
     for (int term = 0; term < 2; ++term) {
       const int base = term == 0 ? kr : -kr;
-      const int A1 = cdiv_p(base + P.mulo, P.rw, P.rw_sh), B1 = fdiv_p(base + P.muhi, P.rw, P.rw_sh);
+      const int A1 = P2 ? -((-(base + P.mulo)) >> P.rw_sh) : cdiv_p(base + P.mulo, P.rw, P.rw_sh);
+      const int B1 = P2 ? (base + P.muhi) >> P.rw_sh : fdiv_p(base + P.muhi, P.rw, P.rw_sh);
       const bool use = term == 0 || pair;
       const bool full = B1 - A1 + 1 >= P.M;
       const int A1m = P2 ? A1 & (P.M - 1) : mod_pos(A1, P.M), B1m = B1 + (A1m - A1);
@@ -2734,7 +2738,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
     const bool has2 = uni_i(cr.I2.w) != 0;
     const int ibase = cr.ibase, sbase = cr.sbase;
     const Cx<float> cc = cr.cc;
-    const double Et = cr.Et;
+    const double Et = uni_d(cr.Et);
     if (wave == NW - 1 && lane == 0) {  // wave 0 is busy with the next candidate
       AtomRec ar;
       ar.w = cr.I0.y;
@@ -2891,14 +2895,14 @@ template <int NT, int SLOTS, int GL, bool P2>
 __global__ void __launch_bounds__(NT) k_mp32(MPArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_next;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = uni_i(threadIdx.x >> 6);
   for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(A.queue, 1);
     __syncthreads();
-    const int qi = s_next;
+    const int qi = uni_i(s_next);
     __syncthreads();
     if (qi >= A.batch) break;
-    mp_signal32<NT, SLOTS, GL, P2>(A, A.order[qi], smem_raw, lane, wave);
+    mp_signal32<NT, SLOTS, GL, P2>(A, uni_i(A.order[qi]), smem_raw, lane, wave);
   }
 }
 
