@@ -108,7 +108,8 @@ def main():
     ap.add_argument("--cpu-signals", type=int, default=16,
                     help="the CPU oracle runs this many signals of the batch, spread over its length range, "
                          "one process per signal on up to 16 host cores (0: skip)")
-    ap.add_argument("--fp64-sample", type=int, default=4, help="signals run on the plain FP64 GPU path")
+    ap.add_argument("--fp64-sample", type=int, default=4,
+                    help="signals run on the plain FP64 GPU path (0 also skips the batched FP64 comparator)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--plan-flags", type=lambda v: int(v, 0), default=None,
@@ -309,6 +310,31 @@ def main():
                     smallest_top2_gap=min(g for g in gap64 if g is not None) if any(
                         g is not None for g in gap64) else None)
 
+    # ---- the whole batch in FP64 (FP64 analysis and loop, one launch): the
+    # comparator at equal batching ----
+    fp64b = None
+    if args.fp64_sample > 0:
+        pb = mpg.Plan(wl.dicts, lengths, wl.eps, mpg.MP_PREC_F64)
+        xb = torch.from_numpy(np.concatenate(xs).astype(np.float64)).to(dev)
+        pb.analyze(xb, stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pb.run(K_CAP, SNR_DB, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms64 = a.elapsed_time(b)
+        n64 = sum(int(pb.info(i).n_atoms) for i in range(len(lengths)))
+        sameb = []
+        for i, r in orc.items():
+            ga = pb.atoms(i)
+            sameb.append(len(ga) == r["n_atoms"] and bool(np.all(
+                (ga["w"] == r["w"]) & (ga["m"] == r["m"]) & (ga["n"] == r["n"]))))
+        fp64b = dict(atoms_per_s=n64 / (ms64 * 1e-3), atoms=n64, loop_ms=ms64,
+                     oracle_signals=list(orc.keys()), identical_to_oracle=sameb if sameb else None)
+        pb.close()
+        del xb
+        log("FP64 batch: %d atoms in %.1f ms" % (n64, ms64))
+
     # ---- a plain device copy of 512 MiB for scale: the HBM rate a streaming kernel reaches ----
     src = torch.empty(1 << 27, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -368,6 +394,8 @@ def main():
         "copy_GB_per_s": copy_gbps,
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (loop_rate / fp64["atoms_per_s"]) if fp64 else None,
+        "fp64_batched": fp64b,
+        "speedup_vs_fp64_batched": (loop_rate / fp64b["atoms_per_s"]) if fp64b else None,
         "accuracy_vs_oracle": acc,
         "paper_context": PAPER_CPU_CONTEXT,
         "counters": {"updated": int(st.updated), "blocks": int(st.blocks), "groups": int(st.l1_groups)},
