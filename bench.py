@@ -642,9 +642,10 @@ def _probe_roofline(tune):
 def _mp32_name(st, p2=True):
     """Name of the FP32 loop kernel a plan launches (p2: every M a power of two);
     32-row tiles have a four-slot instantiation, 8- and 16-row tiles share the
-    two-slot one."""
-    return "mpg::k_mp32<%d, %d, %d, %s>" % (st.threads, 4 if st.tile_rows == 32 else 2, st.group_leaves,
-                                            "true" if p2 else "false")
+    two-slot one; plans whose selections can touch more tree groups than are
+    preloaded load the rest early (last template argument)."""
+    return "mpg::k_mp32<%d, %d, %d, %s, %s>" % (st.threads, 4 if st.tile_rows == 32 else 2, st.group_leaves,
+                                                "true" if p2 else "false", "true" if st.early_groups else "false")
 
 
 def _mp32_key(st, p2=True):

@@ -157,7 +157,10 @@ typedef struct {
   int32_t group_leaves;   /* leaves per tree group of the plan              */
   int32_t threads;        /* threads per workgroup of the MP kernel         */
   int32_t tile_rows;      /* rows per tile of the neighbourhood split       */
-  int32_t pad;
+  int32_t early_groups;   /* 1: the FP32 loop loads the touched tree groups
+                           * beyond the preloaded ones (two per wave) before
+                           * merging, for plans whose selections can touch
+                           * more of them; 0 otherwise (and for FP64 plans) */
 } mp_stats;
 
 /* Creates a plan for `batch` signals of lengths L[0..batch-1] and the W

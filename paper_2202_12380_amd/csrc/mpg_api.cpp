@@ -76,6 +76,7 @@ struct mp_plan {
   std::vector<int32_t> order;
   std::vector<int64_t> frames_total;  // per system, over the batch
   int G = 64, logG = 6, n_groups_max = 0;
+  int64_t tg_bound = 0;  // bound on the tree groups one selection touches
   int nt = 512, grid = 1;
   size_t shmem = 0;
   int64_t total_coef = 0, total_leaves = 0, total_cap = 0, max_Lp = 0;
@@ -670,12 +671,17 @@ int mp_plan_create(const mp_dict* dicts, int32_t W, const int64_t* L, int32_t ba
       // rows updated per selection: the FP32 loop maps row -> frame with an
       // FP32 reciprocal, exact while the row index stays below 2^21
       for (int v = 0; v < W; ++v) {
-        int64_t rows = 0;
+        int64_t rows = 0, tg = 0;
         for (int w = 0; w < W; ++w) {
           const PairDev& P = p->hp[w * W + v];
           if (P.dbox < 0) continue;
           rows += ((int64_t)2 * P.dbox / P.sw + 10) * (((int64_t)dicts[w].M / 2 + ROW) / ROW);
+          // the touched leaves of target w span at most (frames) x (leaves per
+          // frame); each of the two runs (the second one past the wrap) may
+          // straddle one more group boundary
+          tg += ((int64_t)2 * P.dbox / P.sw + 2) * (((int64_t)dicts[w].M / 2 + ROW) / ROW) / p->G + 3;
         }
+        p->tg_bound = std::max(p->tg_bound, tg);
         if (rows >= ((int64_t)1 << 21)) {
           rc = MP_E_LIMIT;
           goto fail;
@@ -928,7 +934,9 @@ static MPArgs mp_args(const mp_plan* p, int64_t max_atoms, double target_snr_db)
   a.roots = p->f64 ? (const void*)p->d_root64 : (const void*)p->d_root32;
   a.n_groups_max = p->n_groups_max;
   a.slot_cap = (p->flags & MP_SCHED_TILE8) ? 1 : ((p->flags & MP_SCHED_TILE32) ? 4 : 2);
-  a.pad3 = 0;
+  // selections that may touch more groups than the loop preloads (two per
+  // wave) get the kernel that loads the rest early
+  a.xpre = p->tg_bound > 2 * (p->nt / 64) ? 1 : 0;
   a.p2 = 1;
   for (int w = 0; w < p->W; ++w)
     if (!is_pow2(p->hd[w].M)) a.p2 = 0;
@@ -1181,6 +1189,7 @@ int mp_get_stats(const mp_plan* p, mp_stats* out) {
   out->group_leaves = p->G;
   out->threads = p->nt;
   out->tile_rows = p->f64 ? 0 : ((p->flags & MP_SCHED_TILE8) ? 8 : ((p->flags & MP_SCHED_TILE32) ? 32 : 16));
+  out->early_groups = (!p->f64 && p->nt == 768 && p->tg_bound > 2 * (p->nt / 64)) ? 1 : 0;
   if (!p->analyzed) return MP_OK;
   if (hipStreamSynchronize(p->last_stream) != hipSuccess) return MP_E_HIP;
   std::vector<SigState> st((size_t)p->batch);

@@ -101,7 +101,8 @@ struct MPArgs {
   int32_t* queue;
   int32_t W, batch, G, logG;
   int32_t n_groups_max, p2;    // p2: every M of the plan is a power of two
-  int32_t slot_cap, pad3;      // 8-row slots per tile of the neighbourhood split (1, 2 or 4)
+  int32_t slot_cap;            // 8-row slots per tile of the neighbourhood split (1, 2 or 4)
+  int32_t xpre;                // 1: touched groups beyond the preloaded ones are loaded before the merges
   int64_t K;
   double snr_db;
   uint32_t partner_gate, pedantic;  // pedantic: select by the pair projection energy (Sec. 5)

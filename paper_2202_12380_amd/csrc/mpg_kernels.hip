@@ -2209,7 +2209,9 @@ __device__ __forceinline__ C4f ld_c4(const Cx<float>* q) {
 __device__ __forceinline__ void st_c4(Cx<float>* q, const C4f& v) { __builtin_memcpy(q, &v, sizeof(C4f)); }
 
 // P2: every M of the plan is a power of two (indices mod M by masks).
-template <int NT, int SLOTS, int GL, bool P2>
+// XP: touched groups beyond the preloaded ones are loaded before the preloaded
+// merges (plans whose selections can touch more groups than are preloaded).
+template <int NT, int SLOTS, int GL, bool P2, bool XP>
 __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lane, int wave) {
   if (A.reset_it > 0 && A.state[s].done) return;  // finished in an earlier round of the reset procedure
   constexpr int NW = NT / 64;
@@ -2843,28 +2845,76 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
       }
       ++c_grp;
     };
-    if (gs0 < TG) merge_slot(gs0, g0, old0);
-    if (gs1 < TG) merge_slot(gs1, g1, old1);
-    // slots beyond the preloaded ones: the leaves in global memory are current
-    for (int gs = NPRE + wave; gs < TG; gs += NW) {
-      int g;
-      if (gs < 64) {
-        g = uni_i(it2[cur].glist[gs]);
-      } else {
+    if constexpr (XP) {
+      // slots beyond the preloaded ones: the leaves in global memory are
+      // current.  The loads of a wave's first two such slots are issued before
+      // its preloaded merges, so that their latency overlaps them.
+      auto slot_group = [&](int gs) -> int {
+        if (gs < 64) return uni_i(it2[cur].glist[gs]);
         const int w = uni_i(__popcll(__ballot(sbase <= gs)) - 1);
         const int4 a = *reinterpret_cast<const int4*>(&tg[w].gA_lo);
         const int c = gs - tg[w].slot_base;
-        g = uni_i(c < a.y ? a.x + c : a.z + (c - a.y));
-      }
-      uint64_t best = 0ull;
+        return uni_i(c < a.y ? a.x + c : a.z + (c - a.y));
+      };
+      auto fold_group = [&](int g, const uint64_t* v) {
+        uint64_t best = 0ull;
 #pragma unroll
-      for (int x = 0; x < LPL; ++x) best = umax64(best, leaves[(uint32_t)(g * GL + lane + 64 * x)]);
-      const uint64_t wm = wave_max_key2<float>(best);
-      if (lane == 0) {
-        gkey[g] = wm;
-        atomicMax((unsigned long long*)&tmax[cur], (unsigned long long)wm);
+        for (int x = 0; x < LPL; ++x) best = umax64(best, v[x]);
+        const uint64_t wm = wave_max_key2<float>(best);
+        if (lane == 0) {
+          gkey[g] = wm;
+          atomicMax((unsigned long long*)&tmax[cur], (unsigned long long)wm);
+        }
+        ++c_grp;
+      };
+      const int gx0 = NPRE + wave, gx1 = NPRE + NW + wave;
+      int ga0 = 0, ga1 = 0;
+      uint64_t ex0[LPL], ex1[LPL];
+      if (gx0 < TG) {
+        ga0 = slot_group(gx0);
+#pragma unroll
+        for (int x = 0; x < LPL; ++x) ex0[x] = leaves[(uint32_t)(ga0 * GL + lane + 64 * x)];
       }
-      ++c_grp;
+      if (gx1 < TG) {
+        ga1 = slot_group(gx1);
+#pragma unroll
+        for (int x = 0; x < LPL; ++x) ex1[x] = leaves[(uint32_t)(ga1 * GL + lane + 64 * x)];
+      }
+      if (gs0 < TG) merge_slot(gs0, g0, old0);
+      if (gs1 < TG) merge_slot(gs1, g1, old1);
+      if (gx0 < TG) fold_group(ga0, ex0);
+      if (gx1 < TG) fold_group(ga1, ex1);
+      for (int gs = NPRE + 2 * NW + wave; gs < TG; gs += NW) {
+        const int g = slot_group(gs);
+        uint64_t v[LPL];
+#pragma unroll
+        for (int x = 0; x < LPL; ++x) v[x] = leaves[(uint32_t)(g * GL + lane + 64 * x)];
+        fold_group(g, v);
+      }
+    } else {
+      if (gs0 < TG) merge_slot(gs0, g0, old0);
+      if (gs1 < TG) merge_slot(gs1, g1, old1);
+      // slots beyond the preloaded ones: the leaves in global memory are current
+      for (int gs = NPRE + wave; gs < TG; gs += NW) {
+        int g;
+        if (gs < 64) {
+          g = uni_i(it2[cur].glist[gs]);
+        } else {
+          const int w = uni_i(__popcll(__ballot(sbase <= gs)) - 1);
+          const int4 a = *reinterpret_cast<const int4*>(&tg[w].gA_lo);
+          const int c = gs - tg[w].slot_base;
+          g = uni_i(c < a.y ? a.x + c : a.z + (c - a.y));
+        }
+        uint64_t best = 0ull;
+#pragma unroll
+        for (int x = 0; x < LPL; ++x) best = umax64(best, leaves[(uint32_t)(g * GL + lane + 64 * x)]);
+        const uint64_t wm = wave_max_key2<float>(best);
+        if (lane == 0) {
+          gkey[g] = wm;
+          atomicMax((unsigned long long*)&tmax[cur], (unsigned long long)wm);
+        }
+        ++c_grp;
+      }
     }
     __syncthreads();
 
@@ -2891,7 +2941,7 @@ __device__ void mp_signal32(const MPArgs& A, int s, unsigned char* smem, int lan
   }
 }
 
-template <int NT, int SLOTS, int GL, bool P2>
+template <int NT, int SLOTS, int GL, bool P2, bool XP>
 __global__ void __launch_bounds__(NT) k_mp32(MPArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_next;
@@ -2902,7 +2952,7 @@ __global__ void __launch_bounds__(NT) k_mp32(MPArgs A) {
     const int qi = uni_i(s_next);
     __syncthreads();
     if (qi >= A.batch) break;
-    mp_signal32<NT, SLOTS, GL, P2>(A, uni_i(A.order[qi]), smem_raw, lane, wave);
+    mp_signal32<NT, SLOTS, GL, P2, XP>(A, uni_i(A.order[qi]), smem_raw, lane, wave);
   }
 }
 
@@ -3306,19 +3356,28 @@ static hipError_t launch_mp_t(const MPArgs& a, int grid, bool preload, hipStream
   return hipGetLastError();
 }
 
-template <int NT, int SLOTS, int GL, bool P2>
+template <int NT, int SLOTS, int GL, bool P2, bool XP>
 static hipError_t launch_mp32_t(const MPArgs& a, int grid, hipStream_t st) {
   const size_t sh = mp32_lds_bytes<NT, GL>(a.n_groups_max);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  CHK(hipFuncSetAttribute((const void*)k_mp32<NT, SLOTS, GL, P2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  CHK(hipFuncSetAttribute((const void*)k_mp32<NT, SLOTS, GL, P2, XP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)sh));
-  k_mp32<NT, SLOTS, GL, P2><<<grid, NT, sh, st>>>(a);
+  k_mp32<NT, SLOTS, GL, P2, XP><<<grid, NT, sh, st>>>(a);
   return hipGetLastError();
 }
 
+// The early loads of the groups beyond the preloaded ones have their own
+// 768-thread kernels (kept apart: their registers change the allocation of
+// the whole loop); 512-thread plans merge those groups as the other kernels do.
 template <int NT, int SLOTS, int GL>
 static hipError_t launch_mp32_p(const MPArgs& a, int grid, hipStream_t st) {
-  return a.p2 ? launch_mp32_t<NT, SLOTS, GL, true>(a, grid, st) : launch_mp32_t<NT, SLOTS, GL, false>(a, grid, st);
+  if constexpr (NT == 768) {
+    if (a.xpre)
+      return a.p2 ? launch_mp32_t<NT, SLOTS, GL, true, true>(a, grid, st)
+                  : launch_mp32_t<NT, SLOTS, GL, false, true>(a, grid, st);
+  }
+  return a.p2 ? launch_mp32_t<NT, SLOTS, GL, true, false>(a, grid, st)
+              : launch_mp32_t<NT, SLOTS, GL, false, false>(a, grid, st);
 }
 
 // LDS bytes of the MP kernel for the launch shape (0: unsupported shape).

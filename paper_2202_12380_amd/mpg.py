@@ -74,7 +74,7 @@ class mp_stats(C.Structure):
     _fields_ = [("atoms", C.c_int64), ("updated", C.c_int64), ("blocks", C.c_int64),
                 ("l1_groups", C.c_int64), ("loop_ms", C.c_double), ("analyze_ms", C.c_double),
                 ("dgt_ms", C.c_double), ("group_leaves", C.c_int32), ("threads", C.c_int32),
-                ("tile_rows", C.c_int32), ("pad", C.c_int32)]
+                ("tile_rows", C.c_int32), ("early_groups", C.c_int32)]
 
 
 EXPORTS = ["mp_plan_create", "mp_analyze", "mp_run", "mp_run_resets",

@@ -414,6 +414,9 @@ def test_mp_fp32_schedules_identical_and_autotune():
     for f in (0, G1, NT, NT | G1, T8, G1 | T8, NT | T8, NT | G1 | T8, NT | T32, NT | G1 | T32):
         plan, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=f)
         st = plan.stats()
+        # the 768-thread 128-leaf plans bound the groups a selection touches
+        # above their 24 preloaded slots: they take the early-load kernel
+        assert st.early_groups == (1 if (st.threads, st.group_leaves) == (768, 128) else 0)
         runs[(st.threads, st.group_leaves, st.tile_rows)] = ga
     assert set(runs) == {(768, 256, 16), (768, 128, 16), (512, 256, 16), (512, 128, 16), (768, 256, 8),
                          (768, 128, 8), (512, 256, 8), (512, 128, 8), (512, 256, 32), (512, 128, 32)}
@@ -435,6 +438,32 @@ def test_mp_fp32_schedules_identical_and_autotune():
     torch.cuda.synchronize()
     for s in range(len(lens)):
         assert np.array_equal(plan.atoms(s), ref[s])
+
+
+def test_mp_fp32_early_group_loads():
+    # windows eight hops long in four systems: a selection of the longest
+    # system touches about 30 tree groups of 256 leaves, more than the 24 the
+    # 768-thread loop preloads, so the plan takes the kernel that loads the
+    # rest before merging; its atoms equal the 512-thread loop's bit for bit
+    # (that kernel merges such groups after the preloaded ones) and the
+    # oracle's within the FP32 rule
+    _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 512, 64, 512), (0, 1024, 128, 1024), (0, 2048, 256, 2048), (0, 4096, 512, 4096)]
+    lens = [16384, 14000]
+    xs = [S.audio_like(L, S.rng(84, i)).astype(np.float32) for i, L in enumerate(lens)]
+    plan, ga = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=0)
+    st = plan.stats()
+    assert (st.threads, st.group_leaves, st.early_groups) == (768, 256, 1)
+    assert st.l1_groups > 12 * st.atoms  # tree groups merged per selection, on average
+    plan5, g5 = gpu_run(dicts, xs, 1e-4, K=0, snr_db=25.0, flags=mpg.MP_SCHED_NT512)
+    st5 = plan5.stats()
+    assert (st5.threads, st5.early_groups) == (512, 0)
+    for a, b in zip(ga, g5):
+        assert np.array_equal(a, b)
+    for i, x in enumerate(xs):
+        orc = oracle_run(dicts, x, 1e-4, snr_db=25.0, x_dtype=np.float32)
+        assert_tolerance(ga[i], orc)
 
 
 def test_mp_fp32_loop_with_fp64_dft():
