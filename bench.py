@@ -374,7 +374,7 @@ def main():
             "plan_flags": args.plan_flags,
             "analysis_dft": _dft_name(args.plan_flags),
             "schedule": {"threads": int(st.threads), "group_leaves": int(st.group_leaves),
-                         "tile_rows": int(st.tile_rows), "autotune": tune},
+                         "tile_rows": int(st.tile_rows), "early_groups": int(st.early_groups), "autotune": tune},
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
@@ -575,7 +575,8 @@ def c5_bench(args):
                    "min_snr_db": float(min(10 * np.log10(i.E0 / max(i.E, 1e-300)) for i in infos)),
                    "max_snr_db": float(max(10 * np.log10(i.E0 / max(i.E, 1e-300)) for i in infos)),
                    "schedule": {"threads": int(st.threads), "group_leaves": int(st.group_leaves),
-                                "tile_rows": int(st.tile_rows), "autotune": tune}},
+                                "tile_rows": int(st.tile_rows), "early_groups": int(st.early_groups),
+                                "autotune": tune}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": _traffic(_mp32_key(st), "c5"),
                      "kernel": _mp32_name(st), "tile_rows": int(st.tile_rows),
