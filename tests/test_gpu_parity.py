@@ -466,6 +466,37 @@ def test_mp_fp32_early_group_loads():
         assert_tolerance(ga[i], orc)
 
 
+def test_resets_fp32_early_group_loads():
+    # the reset procedure (Alg. 2) on a plan that takes the early-load loop
+    # kernel: the same atoms as the 512-thread kernel bit for bit, the true
+    # residual's energy reported, the oracle's composition within the FP32 rule
+    torch = _torch()
+    from paper_2202_12380_amd import mpg
+    dicts = [(0, 512, 64, 512), (0, 1024, 128, 1024), (0, 2048, 256, 2048), (0, 4096, 512, 4096)]
+    lens = [16384, 12000]
+    xs = [S.audio_like(L, S.rng(85, i)).astype(np.float32) for i, L in enumerate(lens)]
+    x = torch.from_numpy(np.concatenate(xs)).cuda()
+    runs = []
+    for flags in (0, mpg.MP_SCHED_NT512):
+        plan = mpg.Plan(dicts, lens, 1e-3, flags)
+        assert plan.stats().early_groups == (1 if flags == 0 else 0)
+        plan.analyze(x)
+        plan.run_resets(100000, 25.0, 300, -6.0)
+        torch.cuda.synchronize()
+        runs.append(plan)
+    for s, xv in enumerate(xs):
+        a, b = runs[0].atoms(s), runs[1].atoms(s)
+        assert np.array_equal(a, b)
+        inf = runs[0].info(s)
+        assert inf.stop_reason == mpg.MP_STOP_SNR
+        xp = np.zeros(inf.L_padded)
+        xp[:len(xv)] = xv.astype(np.float64)
+        yp = runs[0].resynth(s).cpu().numpy()
+        assert abs(np.sum((xp - yp) ** 2) - inf.E) <= 1e-9 * inf.E0
+        orc = O.mp_resets(dicts, xv.astype(np.float64), 1e-3, K=100000, target_db=25.0, reset_it=300, reset_db=-6.0)
+        assert_tolerance(a, orc)
+
+
 def test_mp_fp32_loop_with_fp64_dft():
     # FP32 plan whose analysis DFT runs in FP64 (MP_DFT_F64): the loop follows
     # the FP32 rule, and the initial coefficients are the FP64 ones rounded
